@@ -1,0 +1,130 @@
+"""CPU oracle for the Köhler contrast curve (test infrastructure only).
+
+Only the test suite, the smoke check and the bench's CPU-baseline leg may import this package. The
+product path (the HIP library and its Python binding) never does, and it shares no code with it.
+
+Reference: G. Noyel, arXiv 1707.05062. ``curve`` is the definition of Sec. 2.1 (eqs (1)-(3)) written
+out over every threshold and every ordered neighbour pair; ``alg1`` is Algorithm 1 of Sec. 3.1 over
+the half neighbourhood of Sec. 3.2; ``thresholds`` gives the curve's local maxima and the optimum of
+eq (4). The C sources are in ``kohler_oracle.c``; ``build()`` compiles them with gcc and OpenMP.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kohler_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, E_ARG, E_RANGE, E_CAPACITY = 0, -1, -2, -3
+
+
+def build(src: str = _SRC, out: str = _LIB) -> str:
+    """Compile the oracle into a shared library (plain gcc, -O2, OpenMP; no fast-math)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+           "-o", out, src]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = _bind(ctypes.CDLL(_LIB))
+    return _lib
+
+
+def _bind(lib):
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    f64p = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_curve.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                 i32p, ctypes.c_int32, i64p, i64p, f64p]
+    lib.oracle_curve.restype = ctypes.c_int
+    lib.oracle_alg1.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                i64p, i64p]
+    lib.oracle_alg1.restype = ctypes.c_int
+    lib.oracle_thresholds.argtypes = [i64p, i64p, ctypes.c_int32, i32p, ctypes.c_int32, i32p, i32p]
+    lib.oracle_thresholds.restype = ctypes.c_int
+    return lib
+
+
+def load_library(path: str):
+    """Bind an oracle library built from another source file (used by the mutation tests)."""
+    return _bind(ctypes.CDLL(path))
+
+
+def _ptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: oracle status {status}")
+        self.status = status
+
+
+def curve(img: np.ndarray, M: int, nbhd: int = 4, ts=None, lib=None):
+    """Eqs (1)-(3) by enumeration: returns (sum int64, count int64, C float64) for t in ``ts``
+    (all of 0..M-1 by default)."""
+    lib = lib or _load()
+    f = np.ascontiguousarray(img, dtype=np.int32)
+    if f.ndim != 2:
+        raise ValueError("image must be 2-D")
+    t = np.arange(M, dtype=np.int32) if ts is None else np.ascontiguousarray(ts, dtype=np.int32)
+    s = np.zeros(len(t), np.int64)
+    k = np.zeros(len(t), np.int64)
+    c = np.zeros(len(t), np.float64)
+    st = lib.oracle_curve(_ptr(f, ctypes.c_int32), f.shape[0], f.shape[1], M, nbhd,
+                          _ptr(t, ctypes.c_int32), len(t), _ptr(s, ctypes.c_int64),
+                          _ptr(k, ctypes.c_int64), _ptr(c, ctypes.c_double))
+    if st != OK:
+        raise OracleError(st, "oracle_curve")
+    return s, k, c
+
+
+def alg1(img: np.ndarray, M: int, nbhd: int = 4, lib=None):
+    """Algorithm 1 over the half neighbourhood: returns (sum int64, count int64)."""
+    lib = lib or _load()
+    f = np.ascontiguousarray(img, dtype=np.int32)
+    s = np.zeros(M, np.int64)
+    k = np.zeros(M, np.int64)
+    st = lib.oracle_alg1(_ptr(f, ctypes.c_int32), f.shape[0], f.shape[1], M, nbhd,
+                         _ptr(s, ctypes.c_int64), _ptr(k, ctypes.c_int64))
+    if st != OK:
+        raise OracleError(st, "oracle_alg1")
+    return s, k
+
+
+def thresholds(sum_, count, cap: int | None = None, lib=None):
+    """Local maxima (ascending) and t0 of eq (4) from exact int64 sums and counts.
+
+    Returns (thresholds int32 array, t0, status); with a capacity below the number found the
+    array is truncated and status is E_CAPACITY."""
+    lib = lib or _load()
+    s = np.ascontiguousarray(sum_, dtype=np.int64)
+    k = np.ascontiguousarray(count, dtype=np.int64)
+    M = len(s)
+    cap = M if cap is None else cap
+    thr = np.zeros(max(cap, 1), np.int32)
+    n = ctypes.c_int32(0)
+    t0 = ctypes.c_int32(0)
+    st = lib.oracle_thresholds(_ptr(s, ctypes.c_int64), _ptr(k, ctypes.c_int64), M,
+                               _ptr(thr, ctypes.c_int32), cap, ctypes.byref(n), ctypes.byref(t0))
+    if st not in (OK, E_CAPACITY):
+        raise OracleError(st, "oracle_thresholds")
+    return thr[: min(n.value, cap)].copy(), int(t0.value), st, int(n.value)
+
+
+def full(img: np.ndarray, M: int, nbhd: int = 4, lib=None):
+    """Everything the hot path returns: (sum, count, C, thresholds, t0)."""
+    s, k, c = curve(img, M, nbhd, lib=lib)
+    thr, t0, _, _ = thresholds(s, k, lib=lib)
+    return s, k, c, thr, t0

@@ -1,0 +1,265 @@
+"""Pins for the CPU oracle: checks that tie it to the paper and to mathematics, not to itself.
+
+Each ``pin_*`` function takes an oracle library handle (``None`` = the committed oracle) and raises
+AssertionError on a mismatch. The same functions run against deliberately broken builds of the
+oracle in ``test_oracle_mutants.py`` to show that each plausible mistake is caught.
+
+Sources of truth (G. Noyel, arXiv 1707.05062):
+  - hand-worked examples from the definitions of Sec. 2.1, eqs (1)-(4)  (tests/golden/*.txt);
+  - closed forms: over thresholds, sum_t #B(t) = sum over unordered pairs of |f(p) - f(q)|, and
+    sum_t sum(t) = sum over pairs of floor(d^2 / 4), because for a gap d the contrasts
+    min(d - u, u) for u = 0..d-1 add up to floor(d^2 / 4);
+  - special cases with a closed form (constant image, two-level image, unit ramp);
+  - exact symmetries (transpose, flips, grey-level inversion, grey-level shift);
+  - bounds (0 <= C(t) <= min(t, M-1-t), #B(M-1) = 0);
+  - the half-neighbourhood theorem of Sec. 3.2 (eq (9)) via Algorithm 1 (Sec. 3.1);
+  - the direct route of Sec. 3.1: boundary pixels as the dilation of C_1^t minus C_1^t.
+"""
+from __future__ import annotations
+
+import os
+from fractions import Fraction
+
+import numpy as np
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+# ----------------------------------------------------------------------------------------------
+# golden fixtures
+
+def _parse_line(line: str):
+    key, _, rest = line.partition(" ")
+    return key, rest.split()
+
+
+def load_curve_fixture(name: str) -> dict:
+    d: dict = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = _parse_line(line)
+            d[k] = v
+    H, W = int(d["H"][0]), int(d["W"][0])
+    return dict(
+        image=np.array([int(x) for x in d["image"]], dtype=np.int64).reshape(H, W),
+        M=int(d["M"][0]), nbhd=int(d["nbhd"][0]),
+        sum=np.array([int(x) for x in d["sum"]], np.int64),
+        count=np.array([int(x) for x in d["count"]], np.int64),
+        C=[Fraction(x) for x in d["C"]],
+        thresholds=[int(x) for x in d.get("thresholds", [])],
+        t0=int(d["t0"][0]),
+    )
+
+
+def curve_fixture_names() -> list[str]:
+    return sorted(f for f in os.listdir(GOLDEN) if f.startswith("w") and f.endswith(".txt"))
+
+
+def load_threshold_cases() -> list[dict]:
+    cases, cur = [], {}
+    with open(os.path.join(GOLDEN, "thresholds_rule.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("#"):
+                continue
+            if not line:
+                if cur:
+                    cases.append(cur)
+                cur = {}
+                continue
+            k, v = _parse_line(line)
+            cur[k] = v
+    if cur:
+        cases.append(cur)
+    out = []
+    for c in cases:
+        out.append(dict(name=c["name"][0],
+                        sum=np.array([int(x) for x in c["sum"]], np.int64),
+                        count=np.array([int(x) for x in c["count"]], np.int64),
+                        thresholds=[int(x) for x in c.get("thresholds", [])],
+                        t0=int(c["t0"][0])))
+    return out
+
+
+def pin_golden(lib=None, name: str | None = None):
+    for fname in ([name] if name else curve_fixture_names()):
+        fx = load_curve_fixture(fname)
+        s, k, c = oracle.curve(fx["image"], fx["M"], fx["nbhd"], lib=lib)
+        assert np.array_equal(s, fx["sum"]), (fname, "sum", s, fx["sum"])
+        assert np.array_equal(k, fx["count"]), (fname, "count", k, fx["count"])
+        for t, q in enumerate(fx["C"]):
+            assert c[t] == float(q), (fname, "C", t, c[t], q)
+        thr, t0, _, _ = oracle.thresholds(s, k, lib=lib)
+        assert list(thr) == fx["thresholds"], (fname, "thresholds", thr, fx["thresholds"])
+        assert t0 == fx["t0"], (fname, "t0", t0, fx["t0"])
+
+
+def pin_threshold_rule(lib=None):
+    for case in load_threshold_cases():
+        thr, t0, st, n = oracle.thresholds(case["sum"], case["count"], lib=lib)
+        assert list(thr) == case["thresholds"], (case["name"], thr)
+        assert t0 == case["t0"], (case["name"], t0)
+        assert st == oracle.OK and n == len(case["thresholds"])
+
+
+# ----------------------------------------------------------------------------------------------
+# closed forms, special cases, symmetries, bounds
+
+HALF4 = [(0, 1), (1, 0)]
+HALF8 = HALF4 + [(1, 1), (1, -1)]
+
+
+def pair_gaps(img: np.ndarray, nbhd: int) -> np.ndarray:
+    """|f(p) - f(q)| for every unordered neighbour pair, enumerated by array slicing."""
+    f = np.asarray(img, dtype=np.int64)
+    H, W = f.shape
+    out = []
+    for dy, dx in (HALF4 if nbhd == 4 else HALF8):
+        ys0, ys1 = slice(0, H - dy), slice(dy, H)
+        if dx >= 0:
+            xs0, xs1 = slice(0, W - dx), slice(dx, W)
+        else:
+            xs0, xs1 = slice(-dx, W), slice(0, W + dx)
+        out.append(np.abs(f[ys0, xs0] - f[ys1, xs1]).ravel())
+    return np.concatenate(out) if out else np.zeros(0, np.int64)
+
+
+def pin_closed_form_totals(lib=None, seeds=range(6)):
+    for seed in seeds:
+        rng = np.random.default_rng(1000 + seed)
+        for nbhd in (4, 8):
+            H, W = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+            M = int(rng.choice([2, 3, 7, 16, 64, 256]))
+            img = rng.integers(0, M, size=(H, W))
+            s, k, _ = oracle.curve(img, M, nbhd, lib=lib)
+            d = pair_gaps(img, nbhd)
+            assert int(k.sum()) == int(d.sum()), ("sum count", seed, nbhd)
+            assert int(s.sum()) == int((d * d // 4).sum()), ("sum sum", seed, nbhd)
+
+
+def pin_special_cases(lib=None):
+    rng = np.random.default_rng(7)
+    # constant image: every pair has gap 0, so B(t) is empty for every t
+    for nbhd in (4, 8):
+        img = np.full((5, 7), 3)
+        s, k, c = oracle.curve(img, 8, nbhd, lib=lib)
+        assert not s.any() and not k.any() and not c.any()
+        thr, t0, _, _ = oracle.thresholds(s, k, lib=lib)
+        assert len(thr) == 0 and t0 == -1
+    # two-level image {a < b}: count(t) = P_ab and sum(t) = P_ab * min(b - t, t - a) on [a, b-1]
+    for a, b, M in [(2, 9, 12), (0, 1, 2), (5, 6, 10), (3, 10, 16), (1, 7, 8), (0, 255, 256)]:
+        for nbhd in (4, 8):
+            img = np.where(rng.integers(0, 2, size=(6, 9)) == 1, b, a)
+            P = int((pair_gaps(img, nbhd) > 0).sum())
+            s, k, c = oracle.curve(img, M, nbhd, lib=lib)
+            for t in range(M):
+                inside = a <= t < b
+                assert k[t] == (P if inside else 0), (a, b, t)
+                assert s[t] == (P * min(b - t, t - a) if inside else 0), (a, b, t)
+            thr, t0, _, _ = oracle.thresholds(s, k, lib=lib)
+            if P and b - a >= 2:
+                assert list(thr) == [(a + b) // 2] and t0 == (a + b) // 2, (a, b, thr, t0)
+            else:
+                assert len(thr) == 0 and t0 == -1
+    # unit ramp along rows: every pair has gap 0 or 1, and a gap-1 pair has contrast 0
+    img = np.tile(np.arange(12), (4, 1))
+    s, k, c = oracle.curve(img, 16, 4, lib=lib)
+    assert not s.any() and not c.any()
+    assert list(k[:11]) == [4] * 11 and not k[11:].any()
+
+
+def pin_symmetries(lib=None, seeds=range(4)):
+    for seed in seeds:
+        rng = np.random.default_rng(2000 + seed)
+        H, W = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        M = int(rng.choice([5, 16, 33]))
+        img = rng.integers(0, M, size=(H, W))
+        for nbhd in (4, 8):
+            s, k, _ = oracle.curve(img, M, nbhd, lib=lib)
+            for g in (img.T, img[::-1], img[:, ::-1], img[::-1, ::-1]):
+                s2, k2, _ = oracle.curve(g, M, nbhd, lib=lib)
+                assert np.array_equal(s, s2) and np.array_equal(k, k2), ("geometric", seed, nbhd)
+            # inversion g = M-1-f: sum_g(t) = sum_f(M-1-t), count_g(t) = count_f(M-2-t)
+            si, ki, _ = oracle.curve(M - 1 - img, M, nbhd, lib=lib)
+            assert np.array_equal(si, s[::-1]), ("inversion sum", seed, nbhd)
+            kf = np.concatenate([k[::-1][1:], [0]])  # count_f(M-2-t), with count_f(-1) = 0
+            assert np.array_equal(ki, kf), ("inversion count", seed, nbhd)
+            # shift g = f + c without clipping: both curves move right by c
+            cshift = 3
+            ss, ks, _ = oracle.curve(img + cshift, M + cshift, nbhd, lib=lib)
+            assert np.array_equal(ss[cshift:], s) and not ss[:cshift].any(), ("shift", seed)
+            assert np.array_equal(ks[cshift:], k) and not ks[:cshift].any(), ("shift", seed)
+
+
+def pin_bounds(lib=None, seeds=range(4)):
+    for seed in seeds:
+        rng = np.random.default_rng(3000 + seed)
+        M = int(rng.choice([4, 16, 256]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 12)), int(rng.integers(1, 12))))
+        for nbhd in (4, 8):
+            s, k, c = oracle.curve(img, M, nbhd, lib=lib)
+            t = np.arange(M)
+            assert k[M - 1] == 0 and s[M - 1] == 0
+            assert np.all(c >= 0) and np.all(c <= np.minimum(t, M - 1 - t))
+            assert np.all(c[k == 0] == 0)
+
+
+# ----------------------------------------------------------------------------------------------
+# two other routes to the same integers
+
+def pin_alg1(lib=None, seeds=range(8)):
+    """Eq (9): Algorithm 1 over the half neighbourhood equals the full ordered-pair definition."""
+    for seed in seeds:
+        rng = np.random.default_rng(4000 + seed)
+        M = int(rng.choice([2, 5, 16, 64, 256]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 16)), int(rng.integers(1, 16))))
+        for nbhd in (4, 8):
+            s, k, _ = oracle.curve(img, M, nbhd, lib=lib)
+            s1, k1 = oracle.alg1(img, M, nbhd, lib=lib)
+            assert np.array_equal(s, s1) and np.array_equal(k, k1), ("alg1", seed, nbhd)
+
+
+def direct_by_dilation(img: np.ndarray, M: int, nbhd: int):
+    """The direct route of Sec. 3.1 in plain Python: for each t, the pixels x0 of the boundary are
+    (C_1 dilated by the neighbourhood) minus C_1 (eqs (5)-(6)); each such x0 is paired with its
+    neighbours in C_1 and the contrasts of eq (2) are added up. Exact fractions for C."""
+    H, W = img.shape
+    offs = [(-1, 0), (1, 0), (0, -1), (0, 1)]
+    if nbhd == 8:
+        offs += [(-1, -1), (-1, 1), (1, -1), (1, 1)]
+    sums, counts = [], []
+    for t in range(M):
+        c1 = {(y, x) for y in range(H) for x in range(W) if img[y, x] > t}
+        dil = {(y + dy, x + dx) for (y, x) in c1 for (dy, dx) in offs
+               if 0 <= y + dy < H and 0 <= x + dx < W}
+        border = dil - c1
+        S = K = 0
+        for (y, x) in border:
+            for (dy, dx) in offs:
+                q = (y + dy, x + dx)
+                if q in c1:
+                    S += min(int(img[q]) - t, t - int(img[y, x]))
+                    K += 1
+        sums.append(S)
+        counts.append(K)
+    return np.array(sums, np.int64), np.array(counts, np.int64)
+
+
+def pin_direct_dilation(lib=None, seeds=range(10)):
+    for seed in seeds:
+        rng = np.random.default_rng(5000 + seed)
+        M = int(rng.choice([2, 3, 5, 8]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 6)), int(rng.integers(1, 6))))
+        for nbhd in (4, 8):
+            s, k, _ = oracle.curve(img, M, nbhd, lib=lib)
+            sd, kd = direct_by_dilation(img, M, nbhd)
+            assert np.array_equal(s, sd) and np.array_equal(k, kd), ("dilation", seed, nbhd)
+
+
+ALL_PINS = [pin_golden, pin_threshold_rule, pin_closed_form_totals, pin_special_cases,
+            pin_symmetries, pin_bounds, pin_alg1, pin_direct_dilation]

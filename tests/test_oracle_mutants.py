@@ -1,0 +1,53 @@
+"""Plant plausible mistakes in a copy of the oracle's C source and check that the pins catch each.
+
+The committed oracle is never modified: every mutant is a textual edit of a temporary copy, built
+with the same compiler flags, and run on the CPU only.
+"""
+import os
+
+import pytest
+
+import _pins
+import oracle
+
+MUTANTS = {
+    # eq (1): x0 in C_0^t means f(x0) <= t, x1 in C_1^t means f(x1) > t
+    "c0_strict": ("if (f0 > t) /* x0 must lie in C_0^t */", "if (f0 >= t) /* x0 must lie in C_0^t */"),
+    "c1_nonstrict": ("if (f1 <= t) /* x1 must lie in C_1^t */", "if (f1 < t) /* x1 must lie in C_1^t */"),
+    # eq (2): the minimum of the two steps, with the right signs
+    "max_not_min": ("S += up < down ? up : down;", "S += up < down ? down : up;"),
+    "step_off_by_one": ("const int64_t up = f1 - t, down = t - f0; /* eq (2) */",
+                        "const int64_t up = f1 - t, down = t - f0 + 1; /* eq (2) */"),
+    "dropped_count": ("K += 1;\n                }", "K += 0;\n                }"),
+    # eq (3): numerator and denominator
+    "transposed_division": ("C[k] = K ? (double)S / (double)K : 0.0;", "C[k] = S ? (double)K / (double)S : 0.0;"),
+    # the neighbourhood: a wrong offset index
+    "wrong_offset": ("static const int NB_DY[8] = {-1, 1, 0, 0, -1, -1, 1, 1};",
+                     "static const int NB_DY[8] = {-1, -1, 0, 0, -1, -1, 1, 1};"),
+    # Algorithm 1's threshold range [lo, hi-1]
+    "alg1_range": ("for (int64_t t = lo; t < hi; t++) {", "for (int64_t t = lo; t <= hi && t < M; t++) {"),
+    # threshold rule: report the run's first threshold; ties of eq (4) go to the smallest t
+    "report_run_end": ("thr[found] = a;", "thr[found] = b;"),
+    "t0_last_tie": ("if (cmp_curve(sum[t], count[t], sum[best], count[best]) > 0)",
+                    "if (cmp_curve(sum[t], count[t], sum[best], count[best]) >= 0)"),
+    "float_compare": ("const __int128 l = nu * dv, r = nv * du;",
+                      "const __int128 l = (__int128)((double)nu / (double)du * 1e18), r = (__int128)((double)nv / (double)dv * 1e18);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = oracle.build(str(path), str(tmp_path / "libmutant.so"))
+    lib = oracle.load_library(so)
+    caught = []
+    for pin in _pins.ALL_PINS:
+        try:
+            pin(lib)
+        except (AssertionError, oracle.OracleError) as e:
+            caught.append((pin.__name__, str(e)[:80]))
+    assert caught, f"mutant {name} passed every pin"

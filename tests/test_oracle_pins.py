@@ -1,0 +1,44 @@
+"""The CPU oracle against what the paper and mathematics fix (see tests/_pins.py for the sources)."""
+import pytest
+
+import _pins
+
+
+@pytest.mark.parametrize("name", _pins.curve_fixture_names())
+def test_golden_curves(name):
+    _pins.pin_golden(name=name)
+
+
+def test_threshold_rule():
+    _pins.pin_threshold_rule()
+
+
+def test_closed_form_totals():
+    _pins.pin_closed_form_totals()
+
+
+def test_special_cases():
+    _pins.pin_special_cases()
+
+
+def test_symmetries():
+    _pins.pin_symmetries()
+
+
+def test_bounds():
+    _pins.pin_bounds()
+
+
+def test_half_neighbourhood_alg1():
+    _pins.pin_alg1()
+
+
+def test_direct_dilation_route():
+    _pins.pin_direct_dilation()
+
+
+def test_same_double_fixture_is_meaningful():
+    """The exact-compare fixture only tests something if the two values collide as doubles."""
+    from fractions import Fraction
+    a, b = Fraction(1, 3), Fraction(333333333333333334, 10**18)
+    assert a < b and float(a) == float(b)
