@@ -1,0 +1,227 @@
+"""Köhler contrast-thresholding curve on MI355X (gfx950).
+
+Python binding over the C ABI of ``include/kohler.h`` (``libkohler.so``). Every step of the curve
+runs in the library's HIP kernels; this module only marshals arguments. PyTorch supplies device
+memory and streams.
+
+Reference: G. Noyel, "Speeding up the Köhler's method of contrast thresholding", arXiv 1707.05062.
+For every integer threshold t the library returns the exact sum of the pair contrasts over the
+boundary B(t) (Sec. 2.1, eqs (1)-(2)), #B(t), the mean contrast C(t) (eq (3)), the local maxima of
+C (the multiple thresholds) and the optimum t0 (eq (4)).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import E_ARG, E_BUSY, E_CAPACITY, E_DEVICE, E_NOMEM, E_RANGE, OK, Plan  # noqa: F401
+
+__all__ = ["Context", "CurveResult", "KohlerError", "Plan", "curve", "default_context", "strerror"]
+
+FORM_AUTO, FORM_BAND, FORM_MARG = 0, 1, 2
+
+
+class KohlerError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        super().__init__(f"{what}: {_lib.strerror(status)} ({status})" if what else _lib.strerror(status))
+        self.status = status
+
+
+def strerror(status: int) -> str:
+    return _lib.strerror(status)
+
+
+@dataclass
+class CurveResult:
+    sum: object         # int64[M]
+    count: object       # int64[M]
+    C: object           # float64[M]
+    thresholds: object  # int32[n] (truncated to the capacity)
+    t0: int
+    n_thresholds: int
+    status: int
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(dt) -> int:
+    torch = _torch()
+    if dt in (torch.uint8, np.uint8):
+        return _lib.U8
+    if dt in (getattr(torch, "uint16", None), np.uint16):
+        return _lib.U16
+    raise TypeError(f"unsupported pixel dtype {dt}; use uint8 or uint16")
+
+
+def _image_args(img):
+    """(pointer, dtype code, H, W, pitch, keepalive) for a 2-D torch tensor or numpy array."""
+    torch = _torch()
+    if isinstance(img, torch.Tensor):
+        if img.dim() != 2 or img.stride(1) != 1:
+            raise ValueError("image must be a 2-D tensor with unit column stride")
+        H, W = img.shape
+        pitch = img.stride(0) if H > 1 else W
+        return img.data_ptr(), _dtype_code(img.dtype), int(H), int(W), int(pitch), img
+    a = np.asarray(img)
+    if a.ndim != 2:
+        raise ValueError("image must be 2-D")
+    if a.dtype not in (np.uint8, np.uint16):
+        raise TypeError("numpy images must be uint8 or uint16")
+    a = np.ascontiguousarray(a)
+    H, W = a.shape
+    return a.ctypes.data, _dtype_code(a.dtype.type), int(H), int(W), int(W), a
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Context:
+    """A library context bound to one HIP device (owns device scratch and a stream)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = _lib.load()
+        self._h = ctypes.c_void_p()
+        st = self._lib.kohler_create(ctypes.byref(self._h), int(device))
+        if st != OK:
+            raise KohlerError(st, "kohler_create")
+        self.device = int(device)
+
+    def close(self):
+        if self._h:
+            self._lib.kohler_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- plans -------------------------------------------------------------------------------
+    def set_plan(self, dtype: int, M: int, nbhd: int, form: int = FORM_AUTO, band: int = 0,
+                 block: int = 512, grid: int = 0, px_per_lane: int = 4):
+        pl = Plan(form, band, block, grid, px_per_lane)
+        st = self._lib.kohler_set_plan(self._h, dtype, M, nbhd, ctypes.byref(pl))
+        if st != OK:
+            raise KohlerError(st, "kohler_set_plan")
+
+    def get_plan(self, dtype: int, H: int, W: int, M: int, nbhd: int) -> dict:
+        pl = Plan()
+        st = self._lib.kohler_get_plan(self._h, dtype, H, W, M, nbhd, ctypes.byref(pl))
+        if st != OK:
+            raise KohlerError(st, "kohler_get_plan")
+        return pl.as_dict()
+
+    # -- synchronous -------------------------------------------------------------------------
+    def curve(self, img, M: int, nbhd: int = 4, capacity: int | None = None,
+              check: bool = True) -> CurveResult:
+        """Curve of one image (device tensor or host array); results as numpy arrays."""
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        cap = M if capacity is None else int(capacity)
+        m = max(int(M), 1)  # the library validates M; the buffers only need to exist
+        s = np.zeros(m, np.int64)
+        k = np.zeros(m, np.int64)
+        c = np.zeros(m, np.float64)
+        thr = np.zeros(max(cap, 1), np.int32)
+        n = ctypes.c_int32(0)
+        t0 = ctypes.c_int32(0)
+        i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+        st = self._lib.kohler_curve(
+            self._h, ctypes.c_void_p(ptr), code, H, W, pitch, M, nbhd,
+            s.ctypes.data_as(i64p), k.ctypes.data_as(i64p),
+            c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), thr.ctypes.data_as(i32p), cap,
+            ctypes.byref(n), ctypes.byref(t0))
+        del keep
+        if check and st not in (OK, E_CAPACITY):
+            raise KohlerError(st, "kohler_curve")
+        return CurveResult(s, k, c, thr[: min(n.value, cap)].copy(), int(t0.value), int(n.value), st)
+
+    # -- stream-ordered ----------------------------------------------------------------------
+    def alloc_outputs(self, M: int, capacity: int, n: int | None = None):
+        """Device output tensors for curve_async (n=None) or curve_batch (n images)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        shape = (M,) if n is None else (n, M)
+        m = 1 if n is None else n
+        return dict(
+            sum=torch.zeros(shape, dtype=torch.int64, device=dev),
+            count=torch.zeros(shape, dtype=torch.int64, device=dev),
+            C=torch.zeros(shape, dtype=torch.float64, device=dev),
+            thr=torch.zeros((max(capacity, 1),) if n is None else (n, max(capacity, 1)),
+                            dtype=torch.int32, device=dev),
+            ints=torch.zeros((3 * m,), dtype=torch.int32, device=dev),
+        )
+
+    def curve_async(self, img, M: int, nbhd: int = 4, capacity: int | None = None, out=None,
+                    stream=None):
+        """Enqueue the curve of a device image on `stream` (torch's current stream by default).
+        Returns the output dict: sum, count, C, thr (device tensors) and ints = [n_thr, t0, status]."""
+        torch = _torch()
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        cap = M if capacity is None else int(capacity)
+        out = out or self.alloc_outputs(M, cap)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ints = out["ints"]
+        base = ints.data_ptr()
+        st = self._lib.kohler_curve_async(
+            self._h, ctypes.c_void_p(ptr), code, H, W, pitch, M, nbhd, _ptr(out["sum"]),
+            _ptr(out["count"]), _ptr(out["C"]), _ptr(out["thr"]), cap, ctypes.c_void_p(base),
+            ctypes.c_void_p(base + 4), ctypes.c_void_p(base + 8), ctypes.c_void_p(s.cuda_stream))
+        del keep
+        if st != OK:
+            raise KohlerError(st, "kohler_curve_async")
+        return out
+
+    def curve_batch(self, imgs, M: int, nbhd: int = 4, capacity: int | None = None, out=None,
+                    stream=None):
+        """Enqueue the curves of n device images (one persistent launch). Outputs are [n, M] etc.;
+        ints is [n_thr(n), t0(n), status(n)] concatenated."""
+        torch = _torch()
+        n = len(imgs)
+        cap = M if capacity is None else int(capacity)
+        out = out or self.alloc_outputs(M, cap, n)
+        ptrs = (ctypes.c_void_p * n)()
+        Hs = (ctypes.c_int64 * n)()
+        Ws = (ctypes.c_int64 * n)()
+        Ps = (ctypes.c_int64 * n)()
+        code = None
+        for i, im in enumerate(imgs):
+            p, c, H, W, pitch, _ = _image_args(im)
+            if not isinstance(im, torch.Tensor) or not im.is_cuda:
+                raise ValueError("curve_batch takes device tensors")
+            if code is not None and c != code:
+                raise TypeError("all images of a batch must share one dtype")
+            code = c
+            ptrs[i], Hs[i], Ws[i], Ps[i] = p, H, W, pitch
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ints = out["ints"]
+        base = ints.data_ptr()
+        st = self._lib.kohler_curve_batch(
+            self._h, n, ptrs, Hs, Ws, Ps, code, M, nbhd, _ptr(out["sum"]), _ptr(out["count"]),
+            _ptr(out["C"]), _ptr(out["thr"]), cap, ctypes.c_void_p(base),
+            ctypes.c_void_p(base + 4 * n), ctypes.c_void_p(base + 8 * n),
+            ctypes.c_void_p(s.cuda_stream))
+        if st != OK:
+            raise KohlerError(st, "kohler_curve_batch")
+        return out
+
+
+_default: dict[int, Context] = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def curve(img, M: int, nbhd: int = 4, capacity: int | None = None) -> CurveResult:
+    """Synchronous curve of one image on the default context of device 0."""
+    return default_context(0).curve(img, M, nbhd, capacity)

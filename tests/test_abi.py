@@ -1,0 +1,67 @@
+"""C-ABI checks that need no GPU: the library loads, exports what include/kohler.h declares, and the
+host-side argument checks answer without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kohler.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(kohler_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1707_05062_amd import _lib
+    return _lib.load()
+
+
+def test_header_declares_expected_api():
+    from paper_1707_05062_amd import _lib
+    assert declared_functions() == sorted(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror(lib):
+    for st in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.kohler_strerror(st)
+    assert lib.kohler_strerror(12345) == b"unknown status"
+
+
+def test_host_argument_checks_without_device(lib):
+    from paper_1707_05062_amd import _lib
+    # NULL out-pointer and NULL contexts are rejected before any HIP call
+    assert lib.kohler_create(None, 0) == _lib.E_ARG
+    i64 = ctypes.c_int64(0)
+    i32 = ctypes.c_int32(0)
+    d = ctypes.c_double(0)
+    st = lib.kohler_curve(None, ctypes.c_void_p(1), 1, 4, 4, 4, 256, 4, ctypes.byref(i64),
+                          ctypes.byref(i64), ctypes.byref(d), None, 0, ctypes.byref(i32), ctypes.byref(i32))
+    assert st == _lib.E_ARG
+    st = lib.kohler_curve_async(None, ctypes.c_void_p(1), 1, 4, 4, 4, 256, 4, *([ctypes.c_void_p(8)] * 4),
+                                0, *([ctypes.c_void_p(8)] * 3), None)
+    assert st == _lib.E_ARG
+    pl = _lib.Plan()
+    assert lib.kohler_get_plan(None, 1, 4, 4, 256, 4, ctypes.byref(pl)) == _lib.E_ARG
+    assert lib.kohler_set_plan(None, 1, 256, 4, ctypes.byref(pl)) == _lib.E_ARG
+    lib.kohler_destroy(None)  # no-op
+
+
+def test_header_constants_match_binding():
+    from paper_1707_05062_amd import _lib
+    text = open(HEADER).read()
+    m = re.search(r"#define KOHLER_MAX_M_U16 (\d+)", text)
+    assert int(m.group(1)) == _lib.MAX_M_U16
+    for name, val in [("KOHLER_OK", 0), ("KOHLER_E_ARG", -1), ("KOHLER_E_RANGE", -2),
+                      ("KOHLER_E_CAPACITY", -3), ("KOHLER_E_NOMEM", -4), ("KOHLER_E_DEVICE", -5),
+                      ("KOHLER_E_BUSY", -6), ("KOHLER_U8", 1), ("KOHLER_U16", 2)]:
+        assert re.search(rf"{name}\s*=\s*{val}\b", text), name
