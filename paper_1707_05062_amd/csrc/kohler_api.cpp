@@ -117,6 +117,16 @@ kohler_plan resolve_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, in
     return pl;
 }
 
+// Accumulator replicas for a launch of `grid` workgroups: about 32 workgroups per replica.
+int replicas_for(int grid) { return std::max(1, std::min(kMaxReplicas, grid / 32)); }
+
+// One int64 word per grey level can hold both difference arrays (E * 2^32 + D1) while the image
+// has fewer than 2^30 neighbour pairs.
+bool packable(int64_t H, int64_t W, int32_t nbhd) {
+    const int64_t pairs_bound = (nbhd == 4 ? 2 : 4) * H * W;
+    return pairs_bound < (int64_t(1) << 30);
+}
+
 int64_t strips_of(int64_t W, int px_per_lane) { return (W + 64 * px_per_lane - 1) / (64 * px_per_lane); }
 
 KImage describe(const void *ptr, int dtype, int64_t H, int64_t W, int64_t pitch, int px_per_lane,
@@ -191,10 +201,11 @@ int kohler_create(kohler_ctx **out, int device) {
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipMalloc(&ctx->acc1, sizeof(int64_t) * 2 * kMaxM);
+    const size_t acc1_words = (size_t)kMaxReplicas * (size_t)replica_stride(kMaxM);
+    if (e == hipSuccess) e = hipMalloc(&ctx->acc1, sizeof(int64_t) * acc1_words);
     if (e == hipSuccess) e = hipMalloc(&ctx->done1, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMalloc(&ctx->rflag1, sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(ctx->acc1, 0, sizeof(int64_t) * 2 * kMaxM);
+    if (e == hipSuccess) e = hipMemset(ctx->acc1, 0, sizeof(int64_t) * acc1_words);
     if (e == hipSuccess) e = hipMemset(ctx->done1, 0, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipMemset(ctx->rflag1, 0, sizeof(uint32_t));
     if (e == hipSuccess) e = hipMalloc(&ctx->d_out_sc, sizeof(int64_t) * 2 * kMaxM);
@@ -248,7 +259,7 @@ int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const k
     }
     if (pl.form == FORM_MARG && pl.band == 0) pl.band = 1;
     if (!valid_plan(pl, dtype, M)) return KOHLER_E_ARG;
-    if (lds_bytes(pl.form, M, pl.band) + 1024 > kMaxLdsBytes) return KOHLER_E_ARG;
+    if (lds_bytes(pl.form, M, pl.band, pl.block) > kMaxLdsBytes) return KOHLER_E_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->plans[std::make_tuple(dtype, (int)M, (int)nbhd)] = pl;
     return KOHLER_OK;
@@ -280,6 +291,9 @@ int kohler_curve_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H,
     p.n = 1;
     p.M = M;
     p.cap = thr_capacity;
+    p.packed_acc = packable(H, W, nbhd) ? 1 : 0;
+    p.nrep = replicas_for(pl.grid);
+    p.rep_stride = replica_stride(M);
     p.total_units = p.img0.nunits;
     p.acc = ctx->acc1;
     p.done = ctx->done1;
@@ -370,8 +384,14 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
     if (e != hipSuccess) return pick_status(e);
 
     kohler_plan pl = resolve_plan(ctx, dtype, M, nbhd, 1);
-    // per-image scratch and the descriptor table
-    const size_t acc_words = (size_t)n * 2 * (size_t)M;
+    int64_t total_units = 0;
+    for (int32_t i = 0; i < n; ++i) total_units += strips_of(W[i], pl.px_per_lane) * H[i];
+    pl = resolve_plan(ctx, dtype, M, nbhd, total_units);
+    // per-image scratch (replicas limited to keep it under 64 MiB) and the descriptor table
+    const int64_t rstride = replica_stride(M);
+    int nrep = replicas_for(pl.grid);
+    while (nrep > 1 && (size_t)n * nrep * rstride > ((size_t)8 << 20)) nrep /= 2;
+    const size_t acc_words = (size_t)n * nrep * (size_t)rstride;
     if (acc_words > ctx->batch_acc_words) {
         int st = grow_device(&ctx->accb, ctx->batch_acc_words, acc_words, true);
         if (st != KOHLER_OK) return st;
@@ -407,7 +427,6 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
         ctx->h_table[i] = describe(d_imgs[i], dtype, H[i], W[i], pitch[i], pl.px_per_lane, ustart);
         ustart += ctx->h_table[i].nunits;
     }
-    pl = resolve_plan(ctx, dtype, M, nbhd, ustart);
     e = hipMemcpyAsync(ctx->d_table, ctx->h_table, sizeof(KImage) * n, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return pick_status(e);
 
@@ -417,6 +436,11 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
     p.n = n;
     p.M = M;
     p.cap = thr_capacity;
+    p.packed_acc = 1;
+    for (int32_t i = 0; i < n; ++i)
+        if (!packable(H[i], W[i], nbhd)) p.packed_acc = 0;
+    p.nrep = nrep;
+    p.rep_stride = rstride;
     p.total_units = ustart;
     p.acc = ctx->accb;
     p.done = ctx->doneb;

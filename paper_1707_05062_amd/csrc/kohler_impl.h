@@ -25,9 +25,13 @@ struct KParams {
     const KImage *imgs;   // device table, used when n > 1
     KImage img0;          // inline descriptor, used when n == 1
     int32_t n, M, band, cap;
+    int32_t packed_acc;   // 1: acc holds E * 2^32 + D1 in one word per level (images small enough)
+    int32_t nrep;         // accumulator replicas per image; workgroup b adds into replica b % nrep
+    int64_t rep_stride;   // int64 words between replicas (>= 2M)
     int64_t total_units;
-    int64_t *acc;         // [n][2M] int64: first-difference array of #B(t), then second-difference
-                          // array of the contrast sums; all zero between launches
+    int64_t *acc;         // [n][nrep][rep_stride] int64: per replica, the first-difference array
+                          // of #B(t) then the second-difference array of the contrast sums (or
+                          // both packed in the first M words); all zero between launches
     unsigned long long *done;  // [n] units completed in the current launch; zero between launches
     uint32_t *rflag;      // [n] set when a pixel >= M was seen; zero between launches
     int64_t *sum;
@@ -41,14 +45,46 @@ struct KParams {
 
 enum Form { FORM_BAND = 1, FORM_MARG = 2 };
 
+// Accumulator replicas: spreading the workgroups' global atomics over several copies keeps the
+// number of workgroups that contend for one word small.
+constexpr int kMaxReplicas = 16;
+inline int64_t replica_stride(int M) { return ((int64_t)2 * M + 511) / 512 * 512; }
+
 // Largest grey-level range that fits each form's LDS tables.
 constexpr int kMaxMBand = 256;
 constexpr int kMaxMMarg = 10200;
 constexpr int kMaxBandRows = 64;
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
-// LDS bytes a launch needs for (form, M, band).
-size_t lds_bytes(int form, int M, int band);
+// Workgroup scratch for the block-wide scans and reductions; lives at the end of dynamic LDS so that
+// the histogram table starts at LDS address 0.
+struct BlockScratch {
+    int64_t scan[16];
+    int64_t red_s[16];
+    int64_t red_k[16];
+    int32_t red_t[16];
+    int32_t last;
+    uint32_t next;  // next unclaimed chunk of the workgroup's current segment
+    int32_t pad[2];
+};
+
+// The banded table's rows are 257 words apart, so that the LDS bank of a counter depends on both
+// the gap and the low value (a 256-word stride would put every gap of one low value in one bank).
+constexpr int kRowStride = 257;
+
+// LDS bytes before the BlockScratch: the histogram tables, or the finalize step's arrays (two int64
+// arrays of block + 1 entries and one byte per grey level), whichever is larger; 16-byte aligned.
+__host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int block) {
+    const size_t words = (form == FORM_BAND) ? ((size_t)band + 2) * kRowStride + 768 : 4 * (size_t)M;
+    const size_t table = (words * 4 + 15) & ~(size_t)15;
+    const size_t fin = (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
+    return table > fin ? table : fin;
+}
+
+// LDS bytes a launch needs for (form, M, band, threads per workgroup).
+inline size_t lds_bytes(int form, int M, int band, int block) {
+    return lds_main_bytes(form, M, band, block) + sizeof(BlockScratch);
+}
 
 // Workgroups of this launch family that fit on one compute unit at once.
 int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block);

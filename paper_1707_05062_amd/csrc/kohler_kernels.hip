@@ -37,7 +37,8 @@
 namespace kohler {
 namespace {
 
-constexpr int kRing = 8;  // rows whose loads a wave keeps in flight ahead of the pair work
+constexpr int kRowBatch = 16;  // rows whose loads a wave issues together before using them
+constexpr int kChunk = 16;     // units (rows of a strip) a wave claims at a time
 
 // Explicit address spaces keep loads, stores and atomics on the global (not flat) and LDS paths.
 #define KOHLER_GLOBAL __attribute__((address_space(1)))
@@ -56,7 +57,7 @@ __device__ __forceinline__ KOHLER_GLOBAL T *gptr(T *p) {
     return (KOHLER_GLOBAL T *)p;
 }
 
-enum : int32_t { ST_OK = 0, ST_RANGE = -2, ST_CAPACITY = -3 };
+enum : int32_t { ST_OK = 0, ST_RANGE = -2, ST_CAPACITY = -3, ST_LAYOUT = -5 };
 
 // ------------------------------------------------------------------------------------------------
 // small device helpers
@@ -70,6 +71,11 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v, uint32_t edge) {
     return (uint32_t)__builtin_amdgcn_update_dpp((int)edge, (int)v, 0x138, 0xF, 0xF, false);
 }
 
+// LDS word at a byte address counted from the start of the workgroup's LDS. The kernel declares no
+// static LDS, so its dynamic LDS (the histogram table first) starts at address 0; the kernel checks
+// this at entry.
+__device__ __forceinline__ lds_u32 *lds_at(uint32_t byte_addr) { return (lds_u32 *)(size_t)byte_addr; }
+
 __device__ __forceinline__ void lds_inc(lds_u32 *p) {
     __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -77,11 +83,21 @@ __device__ __forceinline__ void lds_add(lds_u32 *p, uint32_t v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ uint64_t load_agent(const unsigned long long *p) {
-    return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Data shared between workgroups (image accumulators, unit counters, range flags) is only touched
+// with system-scope atomics, which are performed past the per-XCD L2 caches. That keeps every
+// workgroup's view coherent without agent-scope fences, which on this chip write back and
+// invalidate the whole L2. A workgroup makes its contributions visible before it takes its ticket
+// by using returning atomics and waiting for their results.
+#define KOHLER_XSCOPE __HIP_MEMORY_SCOPE_SYSTEM
+
+__device__ __forceinline__ uint64_t load_shared(const unsigned long long *p) {
+    return __hip_atomic_load(gptr(p), __ATOMIC_RELAXED, KOHLER_XSCOPE);
 }
-__device__ __forceinline__ void store_agent(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ void store_shared(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_store(gptr(p), v, __ATOMIC_RELAXED, KOHLER_XSCOPE);
+}
+__device__ __forceinline__ uint64_t add_shared(unsigned long long *p, unsigned long long v) {
+    return __hip_atomic_fetch_add(gptr(p), v, __ATOMIC_RELAXED, KOHLER_XSCOPE);
 }
 
 // sign(C(u) - C(v)) exactly, where C = s / k (0 when k == 0); s, k >= 0, products need 128 bits.
@@ -95,16 +111,10 @@ __device__ __forceinline__ int cmp_curve(int64_t su, int64_t ku, int64_t sv, int
     return 0;
 }
 
-struct BlockScratch {
-    int64_t scan[16];
-    int64_t red_s[16];
-    int64_t red_k[16];
-    int32_t red_t[16];
-    int32_t last;
-};
+typedef KOHLER_LDS BlockScratch LdsScratch;
 
 // Inclusive prefix sum over the workgroup (blockDim.x a multiple of 64, at most 1024 threads).
-__device__ int64_t block_scan(int64_t x, BlockScratch &bs, int64_t &total) {
+__device__ int64_t block_scan(int64_t x, LdsScratch &bs, int64_t &total) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
@@ -141,63 +151,113 @@ struct Packed {
     static constexpr int NW = (K * (int)sizeof(Pix)) / 4;
 };
 
-template <typename Pix, int K>
-__device__ __forceinline__ void load_chunk(const Pix *row, int c, int W, bool vec,
-                                           uint32_t (&w)[Packed<Pix, K>::NW]) {
+// K pixels of one row. Every lane issues its loads unconditionally: a load whose destination
+// another lane's path overwrites while it is in flight, or whose value is used at once, makes the
+// compiler drain every outstanding load, which would serialise the row ring below.
+//   PACKED: one vector load of K pixels (full strips with aligned rows); unpacked when used.
+//   else:   K element loads from clamped, always valid columns; the values beyond the image are
+//           zeroed when used (ragged last strips, misaligned rows).
+template <typename Pix, int K, bool PACKED>
+struct RowSlot {
+    static constexpr int NV = PACKED ? Packed<Pix, K>::NW : K;
+    uint32_t v[NV];
+    uint32_t er, el;
+};
+
+template <typename Pix, int NB, int K, bool FULL, bool PACKED>
+__device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<Pix, K, PACKED> &sl) {
     constexpr int NW = Packed<Pix, K>::NW;
-    if (vec && c + K <= W) {
+    if constexpr (PACKED) {
+        // the last strip of a row is packed only when W is a multiple of K: lanes past the row
+        // end re-read the row's last aligned chunk, and their pairs are masked out
+        const int cv = FULL ? c : min(c, W - K);
         if constexpr (NW == 1) {
-            w[0] = *gptr(reinterpret_cast<const uint32_t *>(row + c));
+            sl.v[0] = *gptr(reinterpret_cast<const uint32_t *>(row + cv));
         } else if constexpr (NW == 2) {
-            const u32x2 t = *gptr(reinterpret_cast<const u32x2 *>(row + c));
-            w[0] = t.x;
-            w[1] = t.y;
+            const u32x2 t = *gptr(reinterpret_cast<const u32x2 *>(row + cv));
+            sl.v[0] = t.x;
+            sl.v[1] = t.y;
         } else {
-            const u32x4 t = *gptr(reinterpret_cast<const u32x4 *>(row + c));
-            w[0] = t.x;
-            w[1] = t.y;
-            w[2] = t.z;
-            w[3] = t.w;
+            const u32x4 t = *gptr(reinterpret_cast<const u32x4 *>(row + cv));
+            sl.v[0] = t.x;
+            sl.v[1] = t.y;
+            sl.v[2] = t.z;
+            sl.v[3] = t.w;
         }
     } else {
-        constexpr int PPW = 4 / (int)sizeof(Pix);
-        constexpr int SH = 8 * (int)sizeof(Pix);
 #pragma unroll
-        for (int q = 0; q < NW; ++q) w[q] = 0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const uint32_t e = (c + k < W) ? (uint32_t)gptr(row)[c + k] : 0u;
-            w[k / PPW] |= e << (SH * (k % PPW));
-        }
+        for (int k = 0; k < K; ++k) sl.v[k] = (uint32_t)gptr(row)[FULL ? c + k : min(c + k, W - 1)];
     }
+    // edge pixels: only lanes 63 (right) and 0 (left) use them, but every lane loads a valid column
+    sl.er = (uint32_t)gptr(row)[FULL ? c + K : min(c + K, W - 1)];
+    if constexpr (NB == 8) sl.el = (uint32_t)gptr(row)[max(c - 1, 0)];
+    else sl.el = 0;
 }
 
-template <typename Pix, int K>
-__device__ __forceinline__ void unpack(const uint32_t (&w)[Packed<Pix, K>::NW], uint32_t (&v)[K]) {
-    constexpr int PPW = 4 / (int)sizeof(Pix);
-    constexpr int SH = 8 * (int)sizeof(Pix);
-    constexpr uint32_t MASK = (sizeof(Pix) == 1) ? 0xFFu : 0xFFFFu;
+// Pixel values of a slot, multiplied by SCALE (a power of two). Values past the row end are
+// whatever was re-read (packed) or 0 (element loads); every pair that uses them is masked.
+template <typename Pix, int K, bool FULL, bool PACKED, uint32_t SCALE>
+__device__ __forceinline__ void slot_pixels(const RowSlot<Pix, K, PACKED> &sl, int c, int W, uint32_t (&px)[K]) {
+    constexpr int SSH = SCALE == 4 ? 2 : 0;
+    if constexpr (PACKED) {
+        constexpr int PPW = 4 / (int)sizeof(Pix);
+        constexpr int SH = 8 * (int)sizeof(Pix);
+        constexpr uint32_t MASK = (sizeof(Pix) == 1) ? 0xFFu : 0xFFFFu;
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = (w[k / PPW] >> (SH * (k % PPW))) & MASK;
+        for (int k = 0; k < K; ++k) px[k] = ((sl.v[k / PPW] >> (SH * (k % PPW))) & MASK) << SSH;
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) px[k] = ((FULL || c + k < W) ? sl.v[k] : 0u) << SSH;
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
 // per-pair accumulators (LDS)
 
-// Joint histogram of (gap, low value) for gaps 1..nb, row stride 256; spill marginals for larger gaps.
+// Joint histogram of (gap d, low value lo), rows kRowStride words apart, one LDS atomic per pair:
+//   row 0        gap-0 pairs (at their value) and invalid pairs outside the image (at their
+//                lane's column); never read back
+//   rows 1..nb   the joint counts of (d, lo)
+//   row nb+1     lo of the pairs with d > nb (their share of hmin)
+// Pixel values arrive multiplied by 4 (kScale), so that with lo4 = 4*lo and d4 = 4*d the LDS byte
+// address of the counter is min(d4, 4*(nb+1)) * 257 + lo4: a pair costs min, sad, min and one
+// multiply-add (the table starts at LDS address 0).
+// Pairs with d > nb still owe hmax and hsum; dmax tracks the lane's largest gap so that a
+// wave-uniform test after each row can run SpillAcc over that row only when some lane needs it.
 struct BandAcc {
-    lds_u32 *band, *smin, *smax, *ssum;
+    lds_u32 *tab;
     uint32_t nb;
-    __device__ __forceinline__ void pair(uint32_t x, uint32_t y, bool valid) {
-        y = valid ? y : x;  // an invalid pair becomes a gap-0 pair, which contributes nothing
-        const uint32_t a = min(x, y);
-        const uint32_t d = max(x, y) - a;
-        if (d - 1u < nb) {
-            lds_inc(&band[(d - 1u) * 256u + a]);
-        } else if (d > nb) {
-            lds_inc(&smin[a]);
-            lds_inc(&smax[a + d]);
-            lds_inc(&ssum[2u * a + d]);
+    uint32_t dmax;  // largest 4*d seen since the last test
+    static constexpr uint32_t kScale = 4;
+    __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
+        if (!valid) {
+            // a pair outside the image lands in row 0 at a word of its own lane: many lanes adding
+            // to one shared word in the same instruction would be serialised
+            x4 = y4 = 4u * (threadIdx.x & 63u);
+        }
+        const uint32_t lo4 = min(x4, y4);
+        const uint32_t d4 = __builtin_amdgcn_sad_u16(x4, y4, 0u);  // |x4 - y4| (both below 2^16)
+        dmax = max(dmax, d4);
+        const uint32_t row4 = min(d4, 4u * (nb + 1u));
+        lds_inc(lds_at(__umul24(row4, (uint32_t)kRowStride) + lo4));
+    }
+    __device__ __forceinline__ bool needs_spill() const { return dmax > 4u * nb; }
+    __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
+    static constexpr bool kPixels = false;
+    static constexpr bool kSpill = true;
+};
+
+// hmax and hsum of the pairs with gap > nb (second pass over a row, rare); values scaled by 4, so
+// 4*hi and 4*(lo + hi) are already byte offsets.
+struct SpillAcc {
+    uint32_t smax, ssum;  // byte addresses of the hmax and hsum spill tables
+    uint32_t nb;
+    static constexpr uint32_t kScale = 4;
+    __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
+        const uint32_t a4 = min(x4, y4), b4 = max(x4, y4);
+        if (valid && b4 - a4 > 4u * nb) {
+            lds_inc(lds_at(smax + b4));
+            lds_inc(lds_at(ssum + a4 + b4));
         }
     }
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
@@ -217,6 +277,10 @@ struct MargAcc {
         if (valid) lds_add(&hdeg[v], deg);
     }
     static constexpr bool kPixels = true;
+    static constexpr bool kSpill = false;
+    static constexpr uint32_t kScale = 1;
+    uint32_t dmax, nb;
+    __device__ __forceinline__ bool needs_spill() const { return false; }
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -259,55 +323,42 @@ __device__ __forceinline__ void row_pairs(const uint32_t (&cur)[K], const uint32
     }
 }
 
-// One row of packed pixels in flight: the lane's K pixels plus the edge pixels lanes 63 and 0 need.
-template <int NW>
-struct RowSlot {
-    uint32_t w[NW];
-    uint32_t er, el;
-};
-
-template <typename Pix, int NB, int K>
-__device__ __forceinline__ void load_slot(const Pix *row, int c, int W, bool vec, int lane,
-                                          RowSlot<Packed<Pix, K>::NW> &sl) {
-    load_chunk<Pix, K>(row, c, W, vec, sl.w);
-    sl.er = 0;
-    sl.el = 0;
-    if (lane == 63 && c + K < W) sl.er = gptr(row)[c + K];
-    if (NB == 8 && lane == 0 && c >= 1) sl.el = gptr(row)[c - 1];
-}
-
-// Rows [r0, r1) of strip s, by one wave. Loads run kRing rows ahead of the pair work: the ring slot
-// of a row is fixed by unrolling, so the ring stays in registers.
-template <typename Pix, int NB, int K, bool CLAMP, bool FULL, class Acc>
-__device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1, Acc &acc,
-                           uint32_t &vmax) {
-    constexpr int NW = Packed<Pix, K>::NW;
+// Rows [r0, r1) of strip s, by one wave, in batches of kRowBatch rows: a batch issues the loads of
+// its rows and of the halo row below before it uses any of them, and uses them in order, so the
+// whole batch is in flight at once and the wait before each row only covers that row. Batches do
+// not depend on each other; other waves on the SIMD hide a batch's first load latency.
+template <typename Pix, int NB, int K, bool CLAMP, bool FULL, bool PACKED, class Acc, class Spill>
+__device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
+                                           Acc &acc, Spill &spill, uint32_t &vmax) {
     constexpr int SW = 64 * K;
     const int lane = threadIdx.x & 63;
     const Pix *base = static_cast<const Pix *>(im.ptr);
     const int64_t H = im.H, pitch = im.pitch;
     const int W = (int)im.W;
     const int c = s * SW + lane * K;
-    const bool vec = im.vec_ok != 0;
 
-    RowSlot<NW> ring[kRing];
+    // last row a batch may touch: the halo row below the range, or the image's last row
+    const int64_t rlast = min(r1, H - 1);
+    for (int64_t rb = r0; rb < r1; rb += kRowBatch) {
+        const int nr = (int)min<int64_t>(kRowBatch, r1 - rb);
+        RowSlot<Pix, K, PACKED> ring[kRowBatch + 1];
+        // unconditional loads (rows past the range re-read rlast, a cache hit): with a fixed number
+        // of loads in flight the compiler can wait for exactly the row it is about to use
 #pragma unroll
-    for (int j = 0; j < kRing; ++j) {
-        const int64_t row = r0 + j;
-        if (row <= r1 && row < H) load_slot<Pix, NB, K>(base + row * pitch, c, W, vec, lane, ring[j]);
-    }
-    for (int64_t r = r0; r < r1; r += kRing) {
+        for (int j = 0; j <= kRowBatch; ++j)
+            load_slot<Pix, NB, K, FULL, PACKED>(base + min(rb + j, rlast) * pitch, c, W, ring[j]);
 #pragma unroll
-        for (int j = 0; j < kRing; ++j) {
-            const int64_t row = r + j;
-            if (row < r1) {
+        for (int j = 0; j < kRowBatch; ++j) {
+            if (j < nr) {
+                const int64_t row = rb + j;
                 const bool has_down = row + 1 < H;
-                const RowSlot<NW> &a = ring[j];
-                const RowSlot<NW> &b = ring[(j + 1) % kRing];
                 uint32_t cur[K], nxt[K];
-                unpack<Pix, K>(a.w, cur);
-                unpack<Pix, K>(b.w, nxt);
-                uint32_t e0 = a.er, e1 = b.er, l1 = b.el;
+                constexpr uint32_t SC = Acc::kScale;
+                slot_pixels<Pix, K, FULL, PACKED, SC>(ring[j], c, W, cur);
+                slot_pixels<Pix, K, FULL, PACKED, SC>(ring[j + 1], c, W, nxt);
+                uint32_t e0 = ((FULL || c + K < W) ? ring[j].er : 0u) * SC;
+                uint32_t e1 = ((FULL || c + K < W) ? ring[j + 1].er : 0u) * SC;
+                uint32_t l1 = ring[j + 1].el * SC;
                 if constexpr (CLAMP) {
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
@@ -320,27 +371,35 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
                     l1 = min(l1, Mm1);
                 }
                 row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, acc);
-                const int64_t nrow = row + kRing;
-                if (nrow <= r1 && nrow < H) load_slot<Pix, NB, K>(base + nrow * pitch, c, W, vec, lane, ring[j]);
+                if constexpr (Acc::kSpill) {
+                    if (__any(acc.needs_spill())) row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, spill);
+                    acc.dmax = 0;
+                }
             }
         }
     }
 }
 
 // Units [la, lb) of one image (image-local, strip-major), by one wave.
-template <typename Pix, int NB, int K, bool CLAMP, class Acc>
+template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
 __device__ __forceinline__ void wave_units(const KImage &im, int64_t la, int64_t lb, uint32_t Mm1, Acc &acc,
-                           uint32_t &vmax) {
+                                           Spill &spill, uint32_t &vmax) {
     constexpr int SW = 64 * K;
     int64_t u = la;
     while (u < lb) {
         const int s = (int)(u / im.H);
         const int64_t r = u - (int64_t)s * im.H;
         const int64_t rend = min(im.H, r + (lb - u));
-        if ((int64_t)(s + 1) * SW < im.W)
-            strip_rows<Pix, NB, K, CLAMP, true>(im, s, r, rend, Mm1, acc, vmax);
-        else
-            strip_rows<Pix, NB, K, CLAMP, false>(im, s, r, rend, Mm1, acc, vmax);
+        if ((int64_t)(s + 1) * SW < im.W) {
+            if (im.vec_ok)
+                strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r, rend, Mm1, acc, spill, vmax);
+            else
+                strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r, rend, Mm1, acc, spill, vmax);
+        } else if (im.vec_ok && im.W % K == 0) {
+            strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r, rend, Mm1, acc, spill, vmax);
+        } else {
+            strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r, rend, Mm1, acc, spill, vmax);
+        }
         u += rend - r;
     }
 }
@@ -348,10 +407,20 @@ __device__ __forceinline__ void wave_units(const KImage &im, int64_t la, int64_t
 // ------------------------------------------------------------------------------------------------
 // histograms -> difference arrays -> global accumulators
 
-__device__ __forceinline__ void add_global(int64_t *p, int64_t v) {
-    if (v != 0)
-        __hip_atomic_fetch_add(gptr(reinterpret_cast<unsigned long long *>(p)), (unsigned long long)v,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// Adds (d1, e) of grey level v. Packed mode: one int64 word per level holds E * 2^32 + D1 (exact
+// while |sum D1| and |sum E| stay below 2^31, which the host guarantees by image size); otherwise
+// D1 and E have a word each. Returns the old value(s) so that the caller can wait for completion.
+__device__ __forceinline__ uint64_t add_levels(int64_t *acc, int M, bool packed, int v, int64_t d1, int64_t e) {
+    unsigned long long *a = reinterpret_cast<unsigned long long *>(acc);
+    uint64_t r = 0;
+    if (packed) {
+        const uint64_t w = ((uint64_t)e << 32) + (uint64_t)d1;
+        if (w != 0) r = add_shared(a + v, w);
+    } else {
+        if (d1 != 0) r = add_shared(a + v, (uint64_t)d1);
+        if (e != 0) r ^= add_shared(a + M + v, (uint64_t)e);
+    }
+    return r;
 }
 
 // E[v] for v >= 1 from the marginals at v-1: hmin + hmax - hsum[2v-3] - 2 hsum[2v-2] - hsum[2v-1].
@@ -363,67 +432,117 @@ __device__ __forceinline__ int64_t second_diff(int64_t lohi, const lds_u32 *hsum
     return e;
 }
 
-__device__ __forceinline__ void merge_band(const KParams &p, lds_u32 *lds, int64_t *acc) {
+__device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, int64_t *acc) {
     const int M = p.M;
     const uint32_t nb = (uint32_t)p.band;
-    lds_u32 *band = lds, *smin = lds + nb * 256u, *smax = smin + 256, *ssum = smax + 256;
-    // project the joint table on rows (hmin), diagonals (hmax) and anti-diagonals (hsum), in place
+    constexpr uint32_t RS = kRowStride;
+    lds_u32 *tab = lds, *lospill = lds + (nb + 1u) * RS, *smax = lds + (nb + 2u) * RS, *ssum = smax + 256;
+    // project rows 1..nb of the (gap, lo) table on rows (hmin), diagonals (hmax) and anti-diagonals
+    // (hsum), adding the large-gap pairs' own counts; results overwrite lospill, smax and ssum.
+    // Four independent partial sums keep several LDS reads in flight per thread.
     for (int x = threadIdx.x; x < 4 * M - 1; x += blockDim.x) {
+        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
         if (x < M) {
             const int v = x;
-            uint32_t r = smin[v];
-            for (uint32_t d = 1; d <= nb; ++d) r += band[(d - 1) * 256u + v];
-            smin[v] = r;
+            uint32_t d = 1;
+            for (; d + 3 <= nb; d += 4) {
+                q0 += tab[d * RS + v];
+                q1 += tab[(d + 1) * RS + v];
+                q2 += tab[(d + 2) * RS + v];
+                q3 += tab[(d + 3) * RS + v];
+            }
+            for (; d <= nb; ++d) q0 += tab[d * RS + v];
+            lospill[v] += q0 + q1 + q2 + q3;
         } else if (x < 2 * M) {
             const int v = x - M;
-            uint32_t q = smax[v];
             const uint32_t dm = min(nb, (uint32_t)v);
-            for (uint32_t d = 1; d <= dm; ++d) q += band[(d - 1) * 256u + v - d];
-            smax[v] = q;
+            uint32_t d = 1;
+            for (; d + 3 <= dm; d += 4) {
+                q0 += tab[d * RS + v - d];
+                q1 += tab[(d + 1) * RS + v - d - 1];
+                q2 += tab[(d + 2) * RS + v - d - 2];
+                q3 += tab[(d + 3) * RS + v - d - 3];
+            }
+            for (; d <= dm; ++d) q0 += tab[d * RS + v - d];
+            smax[v] += q0 + q1 + q2 + q3;
         } else {
             const int s = x - 2 * M;
-            uint32_t q = ssum[s];
             const uint32_t dm = min(nb, (uint32_t)s);
-            for (uint32_t d = 2 - (s & 1); d <= dm; d += 2) q += band[(d - 1) * 256u + (s - d) / 2];
-            ssum[s] = q;
+            uint32_t d = 2 - (s & 1);
+            for (; d + 2 <= dm; d += 4) {
+                q0 += tab[d * RS + (s - d) / 2];
+                q1 += tab[(d + 2) * RS + (s - d - 2) / 2];
+            }
+            for (; d <= dm; d += 2) q0 += tab[d * RS + (s - d) / 2];
+            ssum[s] += q0 + q1;
         }
     }
     __syncthreads();
+    uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
-        add_global(acc + v, (int64_t)smin[v] - (int64_t)smax[v]);
-        if (v >= 1) add_global(acc + M + v, second_diff((int64_t)smin[v - 1] + smax[v - 1], ssum, v, M));
+        const int64_t d1 = (int64_t)lospill[v] - (int64_t)smax[v];
+        const int64_t e = v >= 1 ? second_diff((int64_t)lospill[v - 1] + smax[v - 1], ssum, v, M) : 0;
+        sink ^= add_levels(acc, M, p.packed_acc != 0, v, d1, e);
     }
+    return sink;
 }
 
-__device__ __forceinline__ void merge_marg(const KParams &p, lds_u32 *lds, int64_t *acc) {
+__device__ __forceinline__ uint64_t merge_marg(const KParams &p, lds_u32 *lds, int64_t *acc) {
     const int M = p.M;
     const lds_u32 *hmin = lds, *hdeg = lds + M, *hsum = lds + 2 * M;
+    uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
-        add_global(acc + v, 2 * (int64_t)hmin[v] - (int64_t)hdeg[v]);
-        if (v >= 1) add_global(acc + M + v, second_diff((int64_t)hdeg[v - 1], hsum, v, M));
+        const int64_t d1 = 2 * (int64_t)hmin[v] - (int64_t)hdeg[v];
+        const int64_t e = v >= 1 ? second_diff((int64_t)hdeg[v - 1], hsum, v, M) : 0;
+        sink ^= add_levels(acc, M, p.packed_acc != 0, v, d1, e);
     }
+    return sink;
 }
 
 // ------------------------------------------------------------------------------------------------
 // finalize: prefix sums, C, local maxima and t0 for image i (run by one workgroup)
+//
+// LDS use (the histogram tables are dead by now): two int64 arrays of blockDim + 1 entries holding
+// the current chunk's (sum, count) shifted by one, so each thread sees its left neighbour, then one
+// byte per threshold: bits 0-1 = sign of C(t) - C(t-1) (0 equal, 1 rise, 2 fall), bit 2 = C(t) > 0.
 
-__device__ __forceinline__ void finalize(const KParams &p, int i, KOHLER_LDS int8_t *rel, BlockScratch &bs) {
+__device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, LdsScratch &bs) {
     const int M = p.M, tid = threadIdx.x, nt = blockDim.x;
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * 2 * M);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * p.nrep * p.rep_stride);
+    const int R = p.nrep;
+    const int64_t RS = p.rep_stride;
     int64_t *osum = p.sum + (int64_t)i * M;
     int64_t *ocnt = p.count + (int64_t)i * M;
     double *oC = p.C + (int64_t)i * M;
+    KOHLER_LDS int64_t *csum = reinterpret_cast<KOHLER_LDS int64_t *>(lds);
+    KOHLER_LDS int64_t *ccnt = csum + (nt + 1);
+    KOHLER_LDS uint8_t *flags = reinterpret_cast<KOHLER_LDS uint8_t *>(ccnt + (nt + 1));
 
-    int64_t carK = 0, car1 = 0, car2 = 0, tot;
+    int64_t carK = 0, car1 = 0, car2 = 0, tot, prev_s = 0, prev_k = 0;
+    int32_t bt = -1;
+    int64_t bsum = 0, bcnt = 0;
     for (int b = 0; b < M; b += nt) {
         const int t = b + tid;
         const bool in = t < M;
         int64_t d1 = 0, e = 0;
         if (in) {
-            d1 = (int64_t)load_agent(acc + t);
-            e = (int64_t)load_agent(acc + M + t);
-            store_agent(acc + t, 0);
-            store_agent(acc + M + t, 0);
+            // sum the replicas (the packed form is linear, so packed words add up as well)
+            uint64_t w0 = 0, w1 = 0;
+            for (int r = 0; r < R; ++r) {
+                w0 += load_shared(acc + r * RS + t);
+                if (!p.packed_acc) w1 += load_shared(acc + r * RS + M + t);
+            }
+            for (int r = 0; r < R; ++r) {
+                store_shared(acc + r * RS + t, 0);
+                if (!p.packed_acc) store_shared(acc + r * RS + M + t, 0);
+            }
+            if (p.packed_acc) {
+                d1 = (int64_t)(int32_t)(uint32_t)w0;
+                e = (int64_t)(w0 - (uint64_t)d1) >> 32;
+            } else {
+                d1 = (int64_t)w0;
+                e = (int64_t)w1;
+            }
         }
         const int64_t cnt = carK + block_scan(d1, bs, tot);
         carK += tot;
@@ -431,17 +550,29 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, KOHLER_LDS int
         car1 += tot;
         const int64_t sm = car2 + block_scan(in ? delta : 0, bs, tot);
         car2 += tot;
+        if (tid == 0) {
+            csum[0] = prev_s;
+            ccnt[0] = prev_k;
+        }
+        csum[tid + 1] = sm;
+        ccnt[tid + 1] = cnt;
+        __syncthreads();
         if (in) {
             osum[t] = sm;
             ocnt[t] = cnt;
             oC[t] = cnt ? (double)sm / (double)cnt : 0.0;
+            const int r = (t == 0) ? 0 : cmp_curve(sm, cnt, csum[tid], ccnt[tid]);
+            const int pos = cmp_curve(sm, cnt, 0, 1) > 0;
+            flags[t] = (uint8_t)((r > 0 ? 1 : (r < 0 ? 2 : 0)) | (pos ? 4 : 0));
+            if (bt < 0 || cmp_curve(sm, cnt, bsum, bcnt) > 0) {
+                bt = t;
+                bsum = sm;
+                bcnt = cnt;
+            }
         }
+        prev_s = csum[nt];
+        prev_k = ccnt[nt];
     }
-    __syncthreads();
-
-    // rel[t] = sign(C(t) - C(t-1))
-    for (int t = tid; t < M; t += nt)
-        rel[t] = (int8_t)(t == 0 ? 0 : cmp_curve(osum[t], ocnt[t], osum[t - 1], ocnt[t - 1]));
     __syncthreads();
 
     // local maxima: a run start (t == 0 or a rise) with positive C whose run ends in a fall or at M
@@ -450,27 +581,20 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, KOHLER_LDS int
     for (int b = 0; b < M; b += nt) {
         const int t = b + tid;
         int64_t flag = 0;
-        if (t < M && (t == 0 || rel[t] > 0) && cmp_curve(osum[t], ocnt[t], 0, 1) > 0) {
-            int u = t + 1;
-            while (u < M && rel[u] == 0) ++u;
-            flag = (u == M || rel[u] < 0) ? 1 : 0;
+        if (t < M) {
+            const uint32_t f = flags[t];
+            if ((f & 4u) && (t == 0 || (f & 3u) == 1u)) {
+                int u = t + 1;
+                while (u < M && (flags[u] & 3u) == 0u) ++u;
+                flag = (u == M || (flags[u] & 3u) == 2u) ? 1 : 0;
+            }
         }
         const int64_t pos = found + block_scan(flag, bs, tot) - flag;
         if (flag && pos < p.cap) othr[pos] = t;
         found += tot;
     }
 
-    // t0: smallest t attaining max C
-    int32_t bt = -1;
-    int64_t bsum = 0, bcnt = 0;
-    for (int t = tid; t < M; t += nt) {
-        if (bt < 0 || cmp_curve(osum[t], ocnt[t], bsum, bcnt) > 0) {
-            bt = t;
-            bsum = osum[t];
-            bcnt = ocnt[t];
-        }
-    }
-    // wave reduction, then across waves
+    // t0: smallest t attaining max C (each thread's candidate is the first maximum of its own t's)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const int32_t ot = __shfl_down(bt, off, 64);
@@ -505,9 +629,9 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, KOHLER_LDS int
             }
         }
         if (t0 >= 0 && cmp_curve(s0, k0, 0, 1) <= 0) t0 = -1;
-        const uint32_t rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(gptr(p.rflag + i), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        store_agent(p.done + i, 0);
+        const uint32_t rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
+        __hip_atomic_store(gptr(p.rflag + i), 0u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
+        store_shared(p.done + i, 0);
         p.n_thr[i] = (int32_t)found;
         p.t0[i] = t0;
         p.status[i] = rf ? ST_RANGE : (found > p.cap ? ST_CAPACITY : ST_OK);
@@ -560,20 +684,30 @@ __device__ __forceinline__ KImage image_desc(const KParams &p, int i) {
 template <typename Pix, int NB, int K, int FORM, bool CLAMP>
 __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
     extern __shared__ __align__(16) uint32_t lds_raw[];
-    __shared__ BlockScratch bs;
     lds_u32 *lds = (lds_u32 *)lds_raw;
+    LdsScratch &bs = *reinterpret_cast<LdsScratch *>(
+        reinterpret_cast<KOHLER_LDS uint8_t *>(lds) + lds_main_bytes(FORM, p.M, p.band, (int)blockDim.x));
 
+    if ((uint32_t)(size_t)lds != 0u) {
+        // the LDS layout assumption behind lds_at() does not hold: report, compute nothing
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            for (int i = 0; i < p.n; ++i) p.status[i] = ST_LAYOUT;
+        return;
+    }
     const int G = gridDim.x;
     // consecutive logical workgroups land on the same XCD (the dispatcher deals blocks round-robin)
     const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
     const int64_t U = p.total_units;
     int64_t u = (int64_t)g * U / G;
     const int64_t uend = (int64_t)(g + 1) * U / G;
-    const int nw = blockDim.x >> 6, wid = threadIdx.x >> 6;
+    // the wave index is uniform across a wave; saying so keeps all row and unit bookkeeping in
+    // scalar registers and every row test a scalar branch
+    const int nw = blockDim.x >> 6;
+    const int wid = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t Mm1 = (uint32_t)p.M - 1u;
 
     uint32_t table_words;
-    if constexpr (FORM == FORM_BAND) table_words = (uint32_t)p.band * 256u + 1024u;
+    if constexpr (FORM == FORM_BAND) table_words = (((uint32_t)p.band + 2u) * kRowStride + 768u + 3u) & ~3u;
     else table_words = 4u * (uint32_t)p.M;
 
     while (u < uend) {
@@ -584,42 +718,60 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
 
         for (uint32_t x = threadIdx.x; x < table_words / 4; x += blockDim.x)
             reinterpret_cast<KOHLER_LDS u32x4 *>(lds)[x] = u32x4{0u, 0u, 0u, 0u};
+        if (threadIdx.x == 0) bs.next = 0;
         __syncthreads();
 
+        // waves claim chunks of kChunk units from the segment until none is left, so that a wave
+        // whose rows are costly (many large-gap pairs) does not hold up the others
         const int64_t lbase = u - im.ustart;
-        const int64_t la = lbase + wid * nseg / nw, lb = lbase + (wid + 1) * nseg / nw;
+        const uint32_t nchunks = (uint32_t)((nseg + kChunk - 1) / kChunk);
         uint32_t vmax = 0;
+        auto claim = [&]() -> uint32_t {
+            uint32_t k = 0;
+            if ((threadIdx.x & 63) == 0)
+                k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl(k, 0, 64));
+        };
         if constexpr (FORM == FORM_BAND) {
             const uint32_t nb = (uint32_t)p.band;
-            BandAcc acc{lds, lds + nb * 256u, lds + nb * 256u + 256u, lds + nb * 256u + 512u, nb};
-            wave_units<Pix, NB, K, CLAMP>(im, la, lb, Mm1, acc, vmax);
+            BandAcc acc{lds, nb, 0u};
+            SpillAcc spill{4u * (nb + 2u) * kRowStride, 4u * ((nb + 2u) * kRowStride + 256u), nb};
+            for (uint32_t k = claim(); k < nchunks; k = claim()) {
+                const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
+                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, Mm1 * BandAcc::kScale, acc, spill, vmax);
+            }
+            vmax /= BandAcc::kScale;
         } else {
-            MargAcc acc{lds, lds + p.M, lds + 2 * p.M};
-            wave_units<Pix, NB, K, CLAMP>(im, la, lb, Mm1, acc, vmax);
+            MargAcc acc{lds, lds + p.M, lds + 2 * p.M, 0u, 0u};
+            SpillAcc spill{0u, 0u, 0u};  // not used by the marginal form
+            for (uint32_t k = claim(); k < nchunks; k = claim()) {
+                const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
+                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, Mm1, acc, spill, vmax);
+            }
         }
+        uint64_t sink = 0;
         if constexpr (CLAMP) {
             vmax = wave_max(vmax);
             if ((threadIdx.x & 63) == 0 && vmax > Mm1)
-                __hip_atomic_fetch_or(gptr(p.rflag + i), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                sink = __hip_atomic_fetch_or(gptr(p.rflag + i), 1u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
         }
         __syncthreads();
 
-        int64_t *acc_g = p.acc + (int64_t)i * 2 * p.M;
-        if constexpr (FORM == FORM_BAND) merge_band(p, lds, acc_g);
-        else merge_marg(p, lds, acc_g);
+        int64_t *acc_g = p.acc + ((int64_t)i * p.nrep + (int64_t)(blockIdx.x % (uint32_t)p.nrep)) * p.rep_stride;
+        if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
+        else sink ^= merge_marg(p, lds, acc_g);
 
-        __threadfence();
+        // every contribution of this workgroup has been performed once its returned value is here:
+        // consuming the values makes the wave wait for all of them before the barrier
+        asm volatile("" ::"v"((uint32_t)sink), "v"((uint32_t)(sink >> 32)));
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned long long old = __hip_atomic_fetch_add(
-                gptr(p.done + i), (unsigned long long)nseg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long old = add_shared(p.done + i, (unsigned long long)nseg);
             bs.last = (old + (unsigned long long)nseg == (unsigned long long)im.nunits) ? 1 : 0;
         }
         __syncthreads();
-        if (bs.last) {
-            __threadfence();
-            finalize(p, i, (KOHLER_LDS int8_t *)lds, bs);
-        }
+        if (bs.last) finalize(p, i, lds, bs);
         __syncthreads();
         u = seg_end;
     }
@@ -646,22 +798,14 @@ const void *pick_kernel(int dtype, int nbhd, int form, int px_per_lane, int M) {
 }
 
 hipError_t allow_large_lds(const void *kern) {
-    return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)(kMaxLdsBytes - sizeof(BlockScratch) - 64));
+    return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
 }
 
 }  // namespace
 
-size_t lds_bytes(int form, int M, int band) {
-    size_t words = (form == FORM_BAND) ? (size_t)band * 256 + 1024 : 4 * (size_t)M;
-    size_t bytes = words * 4;
-    const size_t need_fin = ((size_t)M + 15) & ~(size_t)15;  // rel[] of the finalize step
-    return bytes > need_fin ? bytes : need_fin;
-}
-
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,
                         int grid, hipStream_t stream) {
-    const size_t lds = lds_bytes(form, p.M, p.band);
+    const size_t lds = lds_bytes(form, p.M, p.band, block);
     const void *kern = pick_kernel(dtype, nbhd, form, px_per_lane, p.M);
     hipError_t e = allow_large_lds(kern);
     if (e != hipSuccess) return e;
@@ -676,7 +820,7 @@ int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int ban
     const void *kern = pick_kernel(dtype, nbhd, form, px_per_lane, M);
     if (allow_large_lds(kern) != hipSuccess) return 1;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds_bytes(form, M, band)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds_bytes(form, M, band, block)) != hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
