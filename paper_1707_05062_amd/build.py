@@ -25,6 +25,9 @@ HIPCC_FLAGS = [
     "-Wall",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # every uniform-address atomic here is issued by a single lane; the wave-aggregation rewrite
+    # would only add a wait for the result right after issue
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
 ]
 
 

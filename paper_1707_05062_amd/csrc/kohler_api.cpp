@@ -298,6 +298,7 @@ int kohler_curve_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H,
     p.acc = ctx->acc1;
     p.done = ctx->done1;
     p.rflag = ctx->rflag1;
+    p.dyn = 1;
     p.sum = d_sum;
     p.count = d_count;
     p.C = d_C;

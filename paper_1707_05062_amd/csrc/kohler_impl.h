@@ -33,6 +33,8 @@ struct KParams {
                           // of #B(t) then the second-difference array of the contrast sums (or
                           // both packed in the first M words); all zero between launches
     unsigned long long *done;  // [n] units completed in the current launch; zero between launches
+    int32_t dyn;          // 1: one image, chunks dealt round-robin to the workgroups
+    int32_t pad1;
     uint32_t *rflag;      // [n] set when a pixel >= M was seen; zero between launches
     int64_t *sum;
     int64_t *count;
@@ -64,7 +66,7 @@ struct BlockScratch {
     int64_t red_k[16];
     int32_t red_t[16];
     int32_t last;
-    uint32_t next;  // next unclaimed chunk of the workgroup's current segment
+    uint32_t next;   // next unclaimed chunk of the workgroup's current segment
     int32_t pad[2];
 };
 

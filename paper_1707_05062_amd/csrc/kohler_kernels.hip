@@ -37,8 +37,8 @@
 namespace kohler {
 namespace {
 
-constexpr int kRowBatch = 16;  // rows whose loads a wave issues together before using them
-constexpr int kChunk = 16;     // units (rows of a strip) a wave claims at a time
+constexpr int kRowBatch = 8;  // rows whose loads a wave issues together before using them
+constexpr int kChunk = 8;     // units (rows of a strip) a wave claims at a time
 
 // Explicit address spaces keep loads, stores and atomics on the global (not flat) and LDS paths.
 #define KOHLER_GLOBAL __attribute__((address_space(1)))
@@ -135,6 +135,46 @@ __device__ int64_t block_scan(int64_t x, LdsScratch &bs, int64_t &total) {
     total = bs.scan[nw - 1];
     __syncthreads();
     return x;
+}
+
+// Three inclusive prefix sums over the workgroup in one round of barriers.
+__device__ void block_scan3(int64_t (&x)[3], LdsScratch &bs, int64_t (&total)[3]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int64_t y = __shfl_up(x[q], off, 64);
+            if (lane >= off) x[q] += y;
+        }
+    }
+    if (lane == 63) {
+        bs.scan[wid] = x[0];
+        bs.red_s[wid] = x[1];
+        bs.red_k[wid] = x[2];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t r0 = 0, r1 = 0, r2 = 0;
+        for (int w = 0; w < nw; ++w) {
+            r0 += bs.scan[w];
+            bs.scan[w] = r0;
+            r1 += bs.red_s[w];
+            bs.red_s[w] = r1;
+            r2 += bs.red_k[w];
+            bs.red_k[w] = r2;
+        }
+    }
+    __syncthreads();
+    if (wid > 0) {
+        x[0] += bs.scan[wid - 1];
+        x[1] += bs.red_s[wid - 1];
+        x[2] += bs.red_k[wid - 1];
+    }
+    total[0] = bs.scan[nw - 1];
+    total[1] = bs.red_s[nw - 1];
+    total[2] = bs.red_k[nw - 1];
+    __syncthreads();
 }
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
@@ -252,7 +292,6 @@ struct BandAcc {
 struct SpillAcc {
     uint32_t smax, ssum;  // byte addresses of the hmax and hsum spill tables
     uint32_t nb;
-    static constexpr uint32_t kScale = 4;
     __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
         const uint32_t a4 = min(x4, y4), b4 = max(x4, y4);
         if (valid && b4 - a4 > 4u * nb) {
@@ -518,7 +557,15 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
     KOHLER_LDS int64_t *ccnt = csum + (nt + 1);
     KOHLER_LDS uint8_t *flags = reinterpret_cast<KOHLER_LDS uint8_t *>(ccnt + (nt + 1));
 
-    int64_t carK = 0, car1 = 0, car2 = 0, tot, prev_s = 0, prev_k = 0;
+    // the range flag is fetched now, with the accumulators, and used at the very end
+    uint32_t rf = 0;
+    if (tid == 0) rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
+
+    // With P0(t) = sum_{v<=t} E[v] and P1(t) = sum_{v<=t} v E[v], the double prefix sum of E is
+    // sum(t) = (t + 1) P0(t) - P1(t), so count and sum come out of one three-way scan. (int64
+    // arithmetic wraps, but the result is exact because sum(t) itself fits.)
+    const bool one_chunk = M <= nt;  // then the results stay in registers until the end
+    int64_t car[3] = {0, 0, 0}, tot[3], prev_s = 0, prev_k = 0, keep_s = 0, keep_k = 0;
     int32_t bt = -1;
     int64_t bsum = 0, bcnt = 0;
     for (int b = 0; b < M; b += nt) {
@@ -526,15 +573,21 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
         const bool in = t < M;
         int64_t d1 = 0, e = 0;
         if (in) {
-            // sum the replicas (the packed form is linear, so packed words add up as well)
-            uint64_t w0 = 0, w1 = 0;
-            for (int r = 0; r < R; ++r) {
-                w0 += load_shared(acc + r * RS + t);
-                if (!p.packed_acc) w1 += load_shared(acc + r * RS + M + t);
+            // sum the replicas (the packed form is linear, so packed words add up as well); all
+            // loads are issued before any is used (replica indices past R re-read the last one
+            // and are dropped), so the sum costs one memory latency, not R
+            uint64_t v0[kMaxReplicas], v1[kMaxReplicas];
+#pragma unroll
+            for (int r = 0; r < kMaxReplicas; ++r) v0[r] = load_shared(acc + min(r, R - 1) * RS + t);
+            if (!p.packed_acc) {
+#pragma unroll
+                for (int r = 0; r < kMaxReplicas; ++r) v1[r] = load_shared(acc + min(r, R - 1) * RS + M + t);
             }
-            for (int r = 0; r < R; ++r) {
-                store_shared(acc + r * RS + t, 0);
-                if (!p.packed_acc) store_shared(acc + r * RS + M + t, 0);
+            uint64_t w0 = 0, w1 = 0;
+#pragma unroll
+            for (int r = 0; r < kMaxReplicas; ++r) {
+                w0 += r < R ? v0[r] : 0;
+                if (!p.packed_acc) w1 += r < R ? v1[r] : 0;
             }
             if (p.packed_acc) {
                 d1 = (int64_t)(int32_t)(uint32_t)w0;
@@ -544,12 +597,13 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
                 e = (int64_t)w1;
             }
         }
-        const int64_t cnt = carK + block_scan(d1, bs, tot);
-        carK += tot;
-        const int64_t delta = car1 + block_scan(e, bs, tot);
-        car1 += tot;
-        const int64_t sm = car2 + block_scan(in ? delta : 0, bs, tot);
-        car2 += tot;
+        int64_t x[3] = {d1, e, (int64_t)t * e};
+        block_scan3(x, bs, tot);
+        const int64_t cnt = car[0] + x[0];
+        const int64_t P0 = car[1] + x[1], P1 = car[2] + x[2];
+        const int64_t sm = (int64_t)(t + 1) * P0 - P1;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) car[q] += tot[q];
         if (tid == 0) {
             csum[0] = prev_s;
             ccnt[0] = prev_k;
@@ -558,9 +612,14 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
         ccnt[tid + 1] = cnt;
         __syncthreads();
         if (in) {
-            osum[t] = sm;
-            ocnt[t] = cnt;
-            oC[t] = cnt ? (double)sm / (double)cnt : 0.0;
+            if (one_chunk) {
+                keep_s = sm;
+                keep_k = cnt;
+            } else {
+                osum[t] = sm;
+                ocnt[t] = cnt;
+                oC[t] = cnt ? (double)sm / (double)cnt : 0.0;
+            }
             const int r = (t == 0) ? 0 : cmp_curve(sm, cnt, csum[tid], ccnt[tid]);
             const int pos = cmp_curve(sm, cnt, 0, 1) > 0;
             flags[t] = (uint8_t)((r > 0 ? 1 : (r < 0 ? 2 : 0)) | (pos ? 4 : 0));
@@ -589,9 +648,10 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
                 flag = (u == M || (flags[u] & 3u) == 2u) ? 1 : 0;
             }
         }
-        const int64_t pos = found + block_scan(flag, bs, tot) - flag;
+        int64_t ftot;
+        const int64_t pos = found + block_scan(flag, bs, ftot) - flag;
         if (flag && pos < p.cap) othr[pos] = t;
-        found += tot;
+        found += ftot;
     }
 
     // t0: smallest t attaining max C (each thread's candidate is the first maximum of its own t's)
@@ -629,12 +689,23 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
             }
         }
         if (t0 >= 0 && cmp_curve(s0, k0, 0, 1) <= 0) t0 = -1;
-        const uint32_t rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
         __hip_atomic_store(gptr(p.rflag + i), 0u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
         store_shared(p.done + i, 0);
         p.n_thr[i] = (int32_t)found;
         p.t0[i] = t0;
         p.status[i] = rf ? ST_RANGE : (found > p.cap ? ST_CAPACITY : ST_OK);
+    }
+    // stores last, after every barrier, so that no barrier waits for them
+    if (one_chunk && tid < M) {
+        osum[tid] = keep_s;
+        ocnt[tid] = keep_k;
+        oC[tid] = keep_k ? (double)keep_s / (double)keep_k : 0.0;
+    }
+    for (int t = tid; t < M; t += nt) {
+        for (int r = 0; r < R; ++r) {
+            store_shared(acc + r * RS + t, 0);
+            if (!p.packed_acc) store_shared(acc + r * RS + M + t, 0);
+        }
     }
 }
 
@@ -697,58 +768,40 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
     const int G = gridDim.x;
     // consecutive logical workgroups land on the same XCD (the dispatcher deals blocks round-robin)
     const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
-    const int64_t U = p.total_units;
-    int64_t u = (int64_t)g * U / G;
-    const int64_t uend = (int64_t)(g + 1) * U / G;
-    // the wave index is uniform across a wave; saying so keeps all row and unit bookkeeping in
-    // scalar registers and every row test a scalar branch
-    const int nw = blockDim.x >> 6;
-    const int wid = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint32_t Mm1 = (uint32_t)p.M - 1u;
 
     uint32_t table_words;
     if constexpr (FORM == FORM_BAND) table_words = (((uint32_t)p.band + 2u) * kRowStride + 768u + 3u) & ~3u;
     else table_words = 4u * (uint32_t)p.M;
 
-    while (u < uend) {
-        const int i = (p.n == 1) ? 0 : find_image(p, u);
-        const KImage im = image_desc(p, i);
-        const int64_t seg_end = min(uend, im.ustart + im.nunits);
-        const int64_t nseg = seg_end - u;
-
+    auto clear_tables = [&]() {
         for (uint32_t x = threadIdx.x; x < table_words / 4; x += blockDim.x)
             reinterpret_cast<KOHLER_LDS u32x4 *>(lds)[x] = u32x4{0u, 0u, 0u, 0u};
         if (threadIdx.x == 0) bs.next = 0;
         __syncthreads();
+    };
 
-        // waves claim chunks of kChunk units from the segment until none is left, so that a wave
-        // whose rows are costly (many large-gap pairs) does not hold up the others
-        const int64_t lbase = u - im.ustart;
-        const uint32_t nchunks = (uint32_t)((nseg + kChunk - 1) / kChunk);
+    // Runs `chunks(acc, spill, vmax)` with the accumulators of this kernel's form; it must feed every
+    // pair of the units the wave takes on.
+    auto accumulate = [&](auto &&chunks) -> uint32_t {
         uint32_t vmax = 0;
-        auto claim = [&]() -> uint32_t {
-            uint32_t k = 0;
-            if ((threadIdx.x & 63) == 0)
-                k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            return (uint32_t)__builtin_amdgcn_readfirstlane(__shfl(k, 0, 64));
-        };
         if constexpr (FORM == FORM_BAND) {
             const uint32_t nb = (uint32_t)p.band;
             BandAcc acc{lds, nb, 0u};
             SpillAcc spill{4u * (nb + 2u) * kRowStride, 4u * ((nb + 2u) * kRowStride + 256u), nb};
-            for (uint32_t k = claim(); k < nchunks; k = claim()) {
-                const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
-                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, Mm1 * BandAcc::kScale, acc, spill, vmax);
-            }
+            chunks(acc, spill, vmax, Mm1 * BandAcc::kScale);
             vmax /= BandAcc::kScale;
         } else {
             MargAcc acc{lds, lds + p.M, lds + 2 * p.M, 0u, 0u};
             SpillAcc spill{0u, 0u, 0u};  // not used by the marginal form
-            for (uint32_t k = claim(); k < nchunks; k = claim()) {
-                const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
-                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, Mm1, acc, spill, vmax);
-            }
+            chunks(acc, spill, vmax, Mm1);
         }
+        return vmax;
+    };
+
+    // After the pair work of `units` units of image i: range flag, merge into the image's
+    // accumulators, ticket, and the finalize step when this workgroup completed the image.
+    auto flush = [&](int i, const KImage &im, uint32_t vmax, int64_t units) {
         uint64_t sink = 0;
         if constexpr (CLAMP) {
             vmax = wave_max(vmax);
@@ -756,7 +809,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
                 sink = __hip_atomic_fetch_or(gptr(p.rflag + i), 1u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
         }
         __syncthreads();
-
+        if (units == 0) return;  // uniform: nothing to add, and no ticket to take
         int64_t *acc_g = p.acc + ((int64_t)i * p.nrep + (int64_t)(blockIdx.x % (uint32_t)p.nrep)) * p.rep_stride;
         if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
         else sink ^= merge_marg(p, lds, acc_g);
@@ -767,12 +820,67 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (threadIdx.x == 0) {
-            const unsigned long long old = add_shared(p.done + i, (unsigned long long)nseg);
-            bs.last = (old + (unsigned long long)nseg == (unsigned long long)im.nunits) ? 1 : 0;
+            const unsigned long long old = add_shared(p.done + i, (unsigned long long)units);
+            bs.last = (old + (unsigned long long)units == (unsigned long long)im.nunits) ? 1 : 0;
         }
         __syncthreads();
         if (bs.last) finalize(p, i, lds, bs);
         __syncthreads();
+    };
+
+    if (p.dyn) {
+        // One image: chunks of kChunk units are dealt round-robin to the workgroups (chunk c to
+        // logical workgroup c mod G), so every workgroup samples the whole image and costly regions
+        // (many large-gap pairs) spread evenly; waves claim their workgroup's chunks in turn.
+        const KImage im = image_desc(p, 0);
+        const int64_t nchunks = (im.nunits + kChunk - 1) / kChunk;
+        const int64_t mine = g < nchunks ? (nchunks - g + G - 1) / G : 0;  // chunks of this workgroup
+        clear_tables();
+        auto claim = [&]() -> uint32_t {
+            uint32_t k = 0;
+            if ((threadIdx.x & 63) == 0)
+                k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return (uint32_t)__builtin_amdgcn_readfirstlane(k);
+        };
+        const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
+            for (uint32_t j = claim(); j < mine; j = claim()) {
+                const int64_t ca = ((int64_t)g + (int64_t)j * G) * kChunk, cb = min(im.nunits, ca + kChunk);
+                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
+            }
+        });
+        // units of this workgroup: full chunks, less the short last chunk of the image if it is ours
+        int64_t units = mine * kChunk;
+        if (mine > 0 && (nchunks - 1) % G == g) units -= nchunks * kChunk - im.nunits;
+        flush(0, im, vmax, units);
+        return;
+    }
+
+    // Several images: each workgroup takes a contiguous range of the launch's unit space; inside an
+    // image's part of it, waves claim chunks of kChunk units from a workgroup counter.
+    const int64_t U = p.total_units;
+    int64_t u = (int64_t)g * U / G;
+    const int64_t uend = (int64_t)(g + 1) * U / G;
+    while (u < uend) {
+        const int i = (p.n == 1) ? 0 : find_image(p, u);
+        const KImage im = image_desc(p, i);
+        const int64_t seg_end = min(uend, im.ustart + im.nunits);
+        const int64_t nseg = seg_end - u;
+        clear_tables();
+        const int64_t lbase = u - im.ustart;
+        const uint32_t nchunks = (uint32_t)((nseg + kChunk - 1) / kChunk);
+        auto claim = [&]() -> uint32_t {
+            uint32_t k = 0;
+            if ((threadIdx.x & 63) == 0)
+                k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return (uint32_t)__builtin_amdgcn_readfirstlane(k);
+        };
+        const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
+            for (uint32_t k = claim(); k < nchunks; k = claim()) {
+                const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
+                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
+            }
+        });
+        flush(i, im, vmax, nseg);
         u = seg_end;
     }
 }
