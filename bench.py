@@ -1,13 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the Köhler contrast curve on one MI355X.
 
-Default workload (one "step" = the whole hot path for one image: pair formation, per-pair
-accumulation, merge, prefix sums, FP64 division, local maxima and t0, all in one launch):
-  cfg2 - a 3456x5184 (about 18 MP) uint8 synthetic image, M = 256, 4-neighbourhood.
-The image is resident in HBM before the timed region; the timed steps rotate over --rotate
-distinct copies (32 x 17.9 MB = 573 MB) so that the 256 MB Infinity Cache cannot serve them.
+Headline (one "step" = the whole hot path for one image: pair formation, per-pair accumulation,
+merge, prefix sums, FP64 division, local maxima and t0, all in one launch):
+  a 3456x5184 (about 18 MP) uint8 synthetic image, M = 256, 4-neighbourhood.
+The image is resident in HBM before the timed region; the timed steps rotate over --rotate distinct
+copies (32 x 17.9 MB = 573 MB) so that the 256 MB Infinity Cache cannot serve them. The launch plan
+comes from the library's autotuner, run on the image before timing (or from --plan).
 
-Prints ONE JSON line (rank 0) with the throughput in Gpixel/s, the roofline of the kernel
+Also measured in the same run (reported beside the headline, not as separate lines):
+  batched  96 uint8 images of log-uniform sizes (128^2 .. 4000x3000) in one persistent launch vs the
+           plain kernel launched once per image on one stream;
+  served   a Poisson stream of 240 requests/s (70% 1080p video frames, 20% 4K frames, 10% 18 MP
+           stills) through the serving loop vs the same loop restricted to one image per launch,
+           with p50/p99 latency from scheduled arrival to results in host memory, plus a burst that
+           saturates both.
+
+Prints ONE JSON line with the headline throughput in Gpixel/s, the roofline of the curve kernel
 (algorithmic bytes / average kernel duration from HIP events on the launch stream) and the CPU
 oracle's throughput on the host cores (the CPU baseline).
 """
@@ -16,7 +25,9 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import queue
 import sys
+import threading
 import time
 
 import numpy as np
@@ -33,24 +44,40 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(img: np.ndarray, M: int, nbhd: int) -> dict:
+def pct(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+# ------------------------------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands
+
+def cpu_baseline(img: np.ndarray, M: int, nbhd: int, runs: int = 3) -> dict:
     """The oracle (plain brute force of eqs (1)-(3), OpenMP over thresholds) on the host cores."""
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    t = time.perf_counter()
-    oracle.curve(img, M, nbhd)
-    dt = time.perf_counter() - t
+    times = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        oracle.curve(img, M, nbhd)
+        times.append(time.perf_counter() - t)
+    dt = float(np.median(times))
     return {"value": img.size / dt / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
             "seconds": dt,
-            "sample": f"the full {img.shape[0]}x{img.shape[1]} image, all {M} thresholds, one run"}
+            "sample": f"the full {img.shape[0]}x{img.shape[1]} image, all {M} thresholds, "
+                      f"median of {runs} runs"}
 
 
-def run(args) -> dict:
-    import torch
+# ------------------------------------------------------------------------------------------------
+# headline: one 18 MP image per launch
 
-    import gen
-    import paper_1707_05062_amd as K
+def parse_plan(s: str) -> dict:
+    keys = ("form", "band", "block", "grid", "px_per_lane", "replicas")
+    vals = [int(x) for x in s.split(":")]
+    return dict(zip(keys, vals))
 
+
+def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
+    from paper_1707_05062_amd import _lib
     cfg = gen.CONFIGS["cfg2"]
     H, W, M, nbhd = cfg["H"], cfg["W"], cfg["M"], 4
     img = gen.cfg2_image()
@@ -58,7 +85,13 @@ def run(args) -> dict:
     dev = torch.device("cuda", 0)
     src = torch.from_numpy(img).to(dev)
     bufs = [src.clone() for _ in range(max(1, args.rotate))]
-    ctx = K.Context(0)
+    if args.plan:
+        ctx.set_plan(_lib.U8, M, nbhd, **parse_plan(args.plan))
+        tuned = {"source": "--plan"}
+    else:
+        plan, us = ctx.autotune([bufs[0]], M, nbhd, reps=5)
+        tuned = {"source": "autotuner", "plan": plan, "median_us": us}
+        log(f"autotuned plan {plan} {us:.2f} us")
     outs = ctx.alloc_outputs(M, M)
     stream = torch.cuda.current_stream(dev)
 
@@ -71,7 +104,8 @@ def run(args) -> dict:
     sm = outs["sum"].cpu().numpy()
     n_thr, t0, status = [int(x) for x in outs["ints"].cpu()]
     selfcheck = bool(cnt.sum() == gaps.sum() and sm.sum() == (gaps * gaps // 4).sum() and status == 0)
-    log(f"selfcheck={selfcheck} thresholds={n_thr} t0={t0} plan={ctx.get_plan(1, H, W, M, nbhd)}")
+    plan_used = ctx.get_plan(_lib.U8, H, W, M, nbhd)
+    log(f"selfcheck={selfcheck} thresholds={n_thr} t0={t0} plan={plan_used}")
 
     for i in range(args.warmup):
         ctx.curve_async(bufs[i % len(bufs)], M, nbhd, out=outs)
@@ -83,40 +117,32 @@ def run(args) -> dict:
     t_begin = time.perf_counter()
     for i in range(args.steps):
         starts[i].record(stream)
-        ctx.curve_async(bufs[i % len(bufs)], M, nbhd, out=outs)
+        ctx.curve_async(bufs[i % len(bufs)], M, nbhd, out=outs, stream=stream)
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_begin
     durs = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]) * 1e-3  # seconds
 
+    if args.copy_probe:
+        # a plain device copy of known size (one image buffer per dispatch), for scaling the
+        # hardware byte counters of the curve kernel
+        dst = torch.empty_like(src)
+        for b in bufs:
+            dst.copy_(b)
+        torch.cuda.synchronize()
+        log(f"copy probe: {len(bufs)} copies of {src.numel()} bytes")
+
     npx = H * W
-    ms_per_step = wall / args.steps * 1e3
-    value = npx * args.steps / wall / 1e9
     kern = float(durs.mean())
     alg_bytes = npx * 1 + 3 * M * 8 + 4 * n_thr + 12  # pixels read once + curve and thresholds written
     achieved = alg_bytes / kern / 1e9
     log(f"wall {wall:.4f}s for {args.steps} steps; kernel mean {kern*1e6:.2f} us "
         f"p50 {np.median(durs)*1e6:.2f} p99 {np.percentile(durs, 99)*1e6:.2f} us")
-
-    result = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "Gpixel/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int64",
-        "data": "synthetic",
-        "config": {
-            "workload": "cfg2: 3456x5184 uint8, smooth cosine background + 40 ellipses + N(0,5^2) noise, "
-                        "M=256, 4-neighbourhood, one image per launch",
-            "H": H, "W": W, "M": M, "nbhd": nbhd, "rotate_buffers": len(bufs),
-            "plan": ctx.get_plan(1, H, W, M, nbhd),
-        },
+    res = {
+        "value": npx * args.steps / wall / 1e9,
+        "ms_per_step": wall / args.steps * 1e3,
+        "plan": plan_used,
+        "tuning": tuned,
         "frame_ms": {"p50": float(np.median(durs) * 1e3), "p99": float(np.percentile(durs, 99) * 1e3)},
         "roofline": {
             "bound": "hbm",
@@ -124,17 +150,245 @@ def run(args) -> dict:
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": args.traffic_bytes if args.traffic_bytes else None,
             "kernel_us": kern * 1e6,
             "alg_bytes_per_launch": alg_bytes,
         },
         "selfcheck": selfcheck,
+        "H": H, "W": W, "M": M, "nbhd": nbhd, "rotate_buffers": len(bufs),
+    }
+    del bufs
+    return res, img
+
+
+# ------------------------------------------------------------------------------------------------
+# batched: 96 images of uneven sizes, one persistent launch vs one launch per image
+
+def batched(args, K, ctx, torch, gen) -> dict:
+    M, nbhd = 256, 4
+    imgs = gen.batch_images(n=96)
+    npx = sum(im.size for im in imgs)
+    log(f"batch: {len(imgs)} images, {npx / 1e6:.1f} MP")
+    copies = [[torch.from_numpy(im).cuda() for im in imgs] for _ in range(2)]  # 2 x 170 MB > Infinity Cache
+    bctx = K.Context(0)  # its own context: the batch plan is tuned for this workload
+    plan, us = bctx.autotune(copies[0], M, nbhd, reps=3)
+    log(f"batch autotuned plan {plan} {us:.1f} us")
+    pctx = K.Context(0)  # the plain kernel: default plan, grid sized to each image
+    cap = M
+    bout = bctx.alloc_outputs(M, cap, len(imgs))
+    souts = [pctx.alloc_outputs(M, cap) for _ in imgs]
+    stream = torch.cuda.current_stream()
+
+    def run_batch(k):
+        bctx.curve_batch(copies[k % 2], M, nbhd, out=bout)
+
+    def run_plain(k):
+        for i, im in enumerate(copies[k % 2]):
+            pctx.curve_async(im, M, nbhd, out=souts[i], stream=stream)
+
+    def timeit(fn, reps):
+        for k in range(2):
+            fn(k)
+        torch.cuda.synchronize()
+        ts = []
+        for k in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn(k)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        return float(np.median(ts))
+
+    t_b = timeit(run_batch, args.batch_reps)
+    t_p = timeit(run_plain, args.batch_reps)
+    # results of the two paths must agree bit for bit
+    torch.cuda.synchronize()
+    agree = True
+    n = len(imgs)
+    for i in range(n):
+        agree &= bool(torch.equal(bout["sum"][i], souts[i]["sum"]) and torch.equal(bout["count"][i], souts[i]["count"])
+                      and torch.equal(bout["C"][i], souts[i]["C"]))
+    bctx.close()
+    pctx.close()
+    return {"workload": "96 uint8 images, pixel count log-uniform in [128^2, 4000x3000], aspect in "
+                        "{1, 4/3, 16/9}, six-rectangle content + N(0,8^2) noise, M=256, 4-neighbourhood",
+            "images": n, "mpixels": npx / 1e6, "plan": plan,
+            "persistent_ms": t_b * 1e3, "persistent_gpixel_s": npx / t_b / 1e9,
+            "plain_ms": t_p * 1e3, "plain_gpixel_s": npx / t_p / 1e9,
+            "speedup": t_p / t_b, "results_identical": agree}
+
+
+# ------------------------------------------------------------------------------------------------
+# served: Poisson arrivals through the serving loop
+
+SERVE_CLASSES = ("1080p", "4k", "18mp")
+SERVE_MIX = (0.7, 0.2, 0.1)
+
+
+def make_trace(rate: float, seconds: float, seed: int = 5):
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= seconds:
+            break
+        out.append((t, int(rng.choice(3, p=SERVE_MIX))))
+    return out
+
+
+def run_trace(K, ctx, pool, trace, warm_s, server_kw, burst=False):
+    srv = K.Server(ctx, **server_kw)
+    counters = {c: 0 for c in SERVE_CLASSES}
+    try:
+        # one request per class first, so that per-shape graphs exist before the clock starts
+        for c in SERVE_CLASSES:
+            srv.wait(srv.submit(pool[c][0]))
+        tickets: queue.Queue = queue.Queue()
+        t0 = time.monotonic_ns() + 20_000_000
+
+        def submitter():
+            for (ta, ci) in trace:
+                c = SERVE_CLASSES[ci]
+                frame = pool[c][counters[c] % len(pool[c])]
+                counters[c] += 1
+                target = t0 + (0 if burst else int(ta * 1e9))
+                if not burst:
+                    while True:
+                        d = target - time.monotonic_ns()
+                        if d <= 0:
+                            break
+                        if d > 300_000:
+                            time.sleep((d - 200_000) / 1e9)
+                try:
+                    tk = srv.submit(frame)
+                except K.KohlerError as e:
+                    tickets.put((ta, ci, None, e.status))
+                    continue
+                tickets.put((ta, ci, tk, 0))
+            tickets.put(None)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat = {c: [] for c in SERVE_CLASSES}
+        refused, bad, first, last, npx, done = 0, 0, None, None, 0, 0
+        while True:
+            item = tickets.get()
+            if item is None:
+                break
+            ta, ci, tk, st = item
+            if tk is None:
+                refused += 1
+                continue
+            res, info = srv.wait(tk)
+            if res.status != 0:
+                bad += 1
+            arrival = t0 + (0 if burst else int(ta * 1e9))
+            if burst or ta >= warm_s:
+                lat[SERVE_CLASSES[ci]].append((info["t_done_ns"] - arrival) / 1e6)
+                npx += pool[SERVE_CLASSES[ci]][0].shape[0] * pool[SERVE_CLASSES[ci]][0].shape[1]
+                done += 1
+                first = arrival if first is None else min(first, arrival)
+                last = info["t_done_ns"] if last is None else max(last, info["t_done_ns"])
+        th.join()
+        stats = srv.stats()
+    finally:
+        srv.close()
+    span = (last - first) / 1e9 if done else float("nan")
+    alls = [x for c in SERVE_CLASSES for x in lat[c]]
+    out = {"requests": done, "refused": refused, "failed": bad,
+           "req_per_s": done / span, "gpixel_s": npx / span / 1e9,
+           "p50_ms": pct(alls, 50), "p99_ms": pct(alls, 99),
+           "per_class": {c: {"n": len(lat[c]), "p50_ms": pct(lat[c], 50), "p99_ms": pct(lat[c], 99)}
+                         for c in SERVE_CLASSES},
+           "launches": stats["launches"], "graph_launches": stats["graph_launches"],
+           "batched_launches": stats["batched_launches"], "max_batch": stats["max_batch_seen"],
+           "peak_inflight": stats["peak_inflight"]}
+    return out
+
+
+def served(args, K, ctx, torch, gen) -> dict:
+    raw = gen.serve_pool(n1080=args.pool_1080, n4k=args.pool_4k, n18=args.pool_18mp)
+    pool = {c: [torch.from_numpy(f).pin_memory() for f in raw[c]] for c in SERVE_CLASSES}
+    log("serve pool: " + ", ".join(f"{c} x{len(pool[c])}" for c in SERVE_CLASSES))
+    # spot check: the server's result for one frame of each class equals the context call
+    check_srv = K.Server(ctx, slots=4, lanes=1, max_batch=4, hbm_budget_bytes=1 << 30)
+    ok = True
+    for c in SERVE_CLASSES:
+        r, _ = check_srv.wait(check_srv.submit(pool[c][1 % len(pool[c])]))
+        ref = ctx.curve(raw[c][1 % len(raw[c])], 256, 4)
+        ok &= bool(np.array_equal(r.sum, ref.sum) and np.array_equal(r.count, ref.count)
+                   and np.array_equal(r.C, ref.C) and r.t0 == ref.t0)
+    check_srv.close()
+
+    server_kw = dict(slots=32, lanes=2, max_batch=16, use_graphs=True, hbm_budget_bytes=2 << 30)
+    plain_kw = dict(slots=1, lanes=1, max_batch=1, use_graphs=False, hbm_budget_bytes=256 << 20)
+    trace = make_trace(args.rate, args.serve_seconds + 1.0)
+    log(f"served: {len(trace)} arrivals over {args.serve_seconds + 1.0:.0f} s")
+    res = {"workload": f"Poisson arrivals at {args.rate:g}/s for {args.serve_seconds:g} s after 1 s "
+                       "warm-up: 1080p frames 70% (40-blob canvas, window moving 2 px/frame, fresh "
+                       "N(0,6^2) noise), 4K frames 20% (same rule), 18 MP stills 10%; u8, M=256, N4; "
+                       "pinned host frames cycled from a pool; latency = scheduled arrival to "
+                       "results in host memory",
+           "results_match_context": ok,
+           "server_config": server_kw, "plain_config": plain_kw}
+    res["server"] = run_trace(K, ctx, pool, trace, 1.0, server_kw)
+    log(f"served server: {res['server']['p50_ms']:.3f}/{res['server']['p99_ms']:.3f} ms p50/p99")
+    res["plain"] = run_trace(K, ctx, pool, trace, 1.0, plain_kw)
+    log(f"served plain:  {res['plain']['p50_ms']:.3f}/{res['plain']['p99_ms']:.3f} ms p50/p99")
+    rng = np.random.default_rng(55)
+    burst = [(0.0, int(rng.choice(3, p=SERVE_MIX))) for _ in range(args.burst)]
+    res["burst"] = {"requests": len(burst),
+                    "server": run_trace(K, ctx, pool, burst, 0.0, server_kw, burst=True),
+                    "plain": run_trace(K, ctx, pool, burst, 0.0, plain_kw, burst=True)}
+    log(f"burst: server {res['burst']['server']['gpixel_s']:.1f} Gpx/s, "
+        f"plain {res['burst']['plain']['gpixel_s']:.1f} Gpx/s")
+    return res
+
+
+# ------------------------------------------------------------------------------------------------
+
+def run(args) -> dict:
+    import torch
+
+    import gen
+    import paper_1707_05062_amd as K
+
+    ctx = K.Context(0)
+    head, img = headline(args, K, ctx, torch, gen)
+    result = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {
+            "workload": "3456x5184 uint8 (18 MP), smooth 2-D cosine background (amplitude 60) + 40 "
+                        "ellipses with means U[0,255] + N(0,5^2) noise, M=256, 4-neighbourhood, "
+                        "one image per launch",
+            "H": head["H"], "W": head["W"], "M": head["M"], "nbhd": head["nbhd"],
+            "rotate_buffers": head["rotate_buffers"], "plan": head["plan"], "tuning": head["tuning"],
+        },
+        "frame_ms": head["frame_ms"],
+        "roofline": head["roofline"],
+        "selfcheck": head["selfcheck"],
         "paper_context": {"fast_A_gpixel_s": 0.138, "hardware": "Intel i7-4702HQ 4C/8T",
                           "image": "3672x4896 photograph (Table 1)"},
     }
+    if args.only != "headline":
+        result["batched"] = batched(args, K, ctx, torch, gen)
+        result["served"] = served(args, K, ctx, torch, gen)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        result["cpu_baseline"] = cpu_baseline(img, M, nbhd)
+        result["cpu_baseline"] = cpu_baseline(img, head["M"], head["nbhd"])
     ctx.close()
     return result
 
@@ -145,7 +399,21 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rotate", type=int, default=32, help="distinct input buffers cycled by the steps")
+    ap.add_argument("--plan", default="", help="fixed plan form:band:block:grid:px_per_lane:replicas "
+                                               "instead of autotuning")
+    ap.add_argument("--only", choices=["all", "headline"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after timing, copy each input buffer once (a reference for byte counters)")
+    ap.add_argument("--traffic-bytes", type=float, default=0.0,
+                    help="HBM bytes per launch measured by hardware counters for this kernel build")
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--rate", type=float, default=240.0)
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--burst", type=int, default=400)
+    ap.add_argument("--pool-1080", type=int, default=48)
+    ap.add_argument("--pool-4k", type=int, default=12)
+    ap.add_argument("--pool-18mp", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (images are independent; "

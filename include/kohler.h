@@ -60,7 +60,8 @@ enum kohler_status {
     KOHLER_E_CAPACITY = -3, /* more local maxima than thr_capacity */
     KOHLER_E_NOMEM = -4,    /* device or pinned host allocation failed */
     KOHLER_E_DEVICE = -5,   /* a HIP runtime call failed */
-    KOHLER_E_BUSY = -6      /* admission refused (serving: HBM budget or queue full) */
+    KOHLER_E_BUSY = -6,     /* admission refused (serving: HBM budget or queue full) */
+    KOHLER_E_CANCELED = -7  /* serving: the request was cancelled before it ran */
 };
 
 enum kohler_dtype { KOHLER_U8 = 1, KOHLER_U16 = 2 };
@@ -126,10 +127,14 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
 /*
  * Launch plan control (the autotuner's knobs). A plan fixes, for one (dtype, M, nbhd) family:
  *   form        0 = automatic, 1 = banded joint histogram (M <= 256), 2 = marginal histograms
- *   band        number of gap rows of the banded table (2..64; form 1 only)
+ *   band        number of gap rows of the banded table (1..64; form 1 only)
  *   block       threads per workgroup (256 or 512)
  *   grid        workgroups per launch (0 = automatic: enough to fill every compute unit)
- *   px_per_lane pixels each lane loads per row (4 or 8 for KOHLER_U8, 4 for KOHLER_U16)
+ *   px_per_lane pixels each lane loads per row (4 or 8 for KOHLER_U8, 4 for KOHLER_U16); a tile is
+ *               one row of a strip of 64 * px_per_lane columns
+ *   replicas    merge schedule: copies of the per-image device accumulators that the workgroups'
+ *               partial histograms are added into (1..16; 0 = automatic, about one per 32
+ *               workgroups); the finishing workgroup sums the copies
  * kohler_set_plan stores a plan in the context for later calls (KOHLER_E_ARG if it is invalid);
  * kohler_get_plan reports the plan a call with these parameters would use.
  */
@@ -139,11 +144,126 @@ typedef struct kohler_plan {
     int32_t block;
     int32_t grid;
     int32_t px_per_lane;
+    int32_t replicas;
 } kohler_plan;
 
 int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const kohler_plan *plan);
 int kohler_get_plan(kohler_ctx *ctx, int dtype, int64_t H, int64_t W, int32_t M, int32_t nbhd,
                     kohler_plan *plan);
+
+/*
+ * Autotuner. Times candidate plans for the (dtype, M, nbhd) family on a representative workload
+ * and stores the fastest in the context, as kohler_set_plan would. The workload is described as in
+ * kohler_curve_batch (n device images; n == 1 tunes the single-image launch, n > 1 the batched
+ * one). The search is a coordinate descent, two passes over the knobs in the order tile shape
+ * (form and band), px_per_lane, block, grid (automatic or 1..4 workgroups per compute unit) and
+ * replicas, starting from the default plan; each candidate gets two warm-up launches and `reps`
+ * timed ones (0 means 5) on the context's stream, and its median time counts.
+ *   best     out: the chosen plan (grid and replicas may be 0 = automatic)
+ *   best_us  out (may be NULL): its median launch time in microseconds
+ * It allocates and frees temporary device outputs and synchronises the context's stream, so it
+ * belongs to set-up, not to a serving loop. Returns KOHLER_OK, KOHLER_E_ARG (bad workload), or a
+ * launch/device error, in which case the context's previous plan for the family is restored.
+ */
+int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const int64_t *H,
+                    const int64_t *W, const int64_t *pitch, int dtype, int32_t M, int32_t nbhd,
+                    int32_t reps, kohler_plan *best, double *best_us);
+
+/*
+ * ------------------------------------------------------------------------------------------------
+ * Serving. A server runs a request loop on one context's device: callers submit images as they
+ * arrive and collect each result by ticket. A scheduler thread admits queued requests in arrival
+ * order whenever a device slot and enough of the image arena are free (continuous batching: work
+ * that arrives while other requests are on the GPU joins the next launch, without waiting for a
+ * batch to fill), and launches them on one of its streams ("lanes") as soon as a lane is idle.
+ * Requests admitted together run in ONE persistent launch (the batched kernel); a request admitted
+ * alone replays a HIP graph (host-to-device copy, kernel, device-to-host copy of its results) built
+ * once per image shape and lane. Launches on different lanes overlap on the device. Each request's
+ * difference arrays and curve stay in its slot's device memory; the server's device memory (slot
+ * state plus the image arena) never exceeds hbm_budget_bytes. A request's result does not depend
+ * on what it was batched with (every image is independent, Sec. 2.1).
+ *
+ * The family (dtype, M, nbhd) is fixed per server; launch plans come from the context (so a tuned
+ * plan applies). The context must outlive the server; the server does not use the context's
+ * scratch or stream, so the context stays usable for other calls.
+ */
+typedef struct kohler_server kohler_server;
+
+typedef struct kohler_server_config {
+    int32_t dtype, M, nbhd;    /* the family served */
+    int32_t slots;             /* requests resident on the device at once (1..1024) */
+    int32_t lanes;             /* streams launches go to; one launch in flight per lane (1..8) */
+    int32_t max_batch;         /* most requests in one launch (1..slots) */
+    int32_t queue_capacity;    /* waiting requests beyond which submit refuses (>= 1) */
+    int32_t thr_capacity;      /* thresholds kept per request (0..M) */
+    int32_t use_graphs;        /* nonzero: a request admitted alone replays a per-shape HIP graph */
+    int32_t pad;
+    int64_t hbm_budget_bytes;  /* device bytes for slot state plus the image arena (> slot state) */
+} kohler_server_config;
+
+/* What happened to one request; times are CLOCK_MONOTONIC nanoseconds. */
+typedef struct kohler_request_info {
+    int32_t status;       /* the request's status (as kohler_curve returns it) */
+    int32_t n_thresholds; /* number of local maxima (may exceed the capacity) */
+    int32_t t0;
+    int32_t batch;        /* requests in the launch that computed it */
+    int32_t graph;        /* 1 if it ran as a graph replay */
+    int32_t pad;
+    int64_t t_submit_ns, t_launch_ns, t_done_ns;  /* t_done: results in host memory, seen by the server */
+} kohler_request_info;
+
+typedef struct kohler_server_counters {
+    int64_t submitted, completed, refused, cancelled;
+    int64_t launches, graph_launches, batched_launches, graphs_built;
+    int64_t max_batch_seen, peak_inflight;  /* peak_inflight: most requests on the device at once */
+    int64_t arena_bytes, arena_peak_bytes, slot_state_bytes;
+} kohler_server_counters;
+
+/*
+ * Create a server on ctx's device. Allocates, once, the slot state (per slot: accumulator replicas,
+ * counters, a result record, and its pinned host mirror), the image arena (the rest of the budget)
+ * and the lanes, and starts the scheduler thread. Returns KOHLER_OK, KOHLER_E_ARG (bad config or a
+ * budget that does not cover the slot state), KOHLER_E_NOMEM or KOHLER_E_DEVICE.
+ */
+int kohler_server_create(kohler_ctx *ctx, const kohler_server_config *cfg, kohler_server **out);
+
+/* Stop the scheduler after the launches in flight complete, drop queued requests and results not
+ * yet collected, and free everything. NULL is a no-op. */
+void kohler_server_destroy(kohler_server *srv);
+
+/*
+ * Submit one image (H rows of `pitch` elements of the server's dtype). A device or pinned host
+ * image is read in place and must stay valid and unchanged until the request completes; a pageable
+ * host image is copied into pinned staging before this returns. Returns KOHLER_OK and a ticket,
+ * KOHLER_E_ARG (bad shape), or KOHLER_E_BUSY when the queue is full or the image alone exceeds the
+ * image arena (then no ticket is issued).
+ */
+int kohler_server_submit(kohler_server *srv, const void *img, int64_t H, int64_t W, int64_t pitch,
+                         uint64_t *ticket);
+
+/* 1 if the request has completed (or was cancelled), 0 if not yet, KOHLER_E_ARG for an unknown
+ * ticket. Never blocks. */
+int kohler_server_poll(kohler_server *srv, uint64_t ticket);
+
+/*
+ * Block until the request completes, copy its results to HOST arrays (sum, count: M int64; C: M
+ * doubles; thresholds: up to thr_capacity int32 — each may be NULL to skip it), fill *info (may be
+ * NULL) and release the ticket (one waiter per ticket). Returns the request's status (KOHLER_OK, KOHLER_E_RANGE,
+ * KOHLER_E_CAPACITY, KOHLER_E_CANCELED, KOHLER_E_DEVICE) or KOHLER_E_ARG for an unknown ticket.
+ */
+int kohler_server_wait(kohler_server *srv, uint64_t ticket, int64_t *sum, int64_t *count, double *C,
+                       int32_t *thresholds, int32_t thr_capacity, kohler_request_info *info);
+
+/* Cancel a request that is still queued: KOHLER_OK (its wait then returns KOHLER_E_CANCELED),
+ * KOHLER_E_BUSY if it is already on the device or done, KOHLER_E_ARG for an unknown ticket. */
+int kohler_server_cancel(kohler_server *srv, uint64_t ticket);
+
+/* Hold (paused != 0) or release admission. Queued requests wait while admission is held; the
+ * launches in flight complete. Returns KOHLER_OK or KOHLER_E_ARG. */
+int kohler_server_pause(kohler_server *srv, int32_t paused);
+
+/* Counters since creation. Returns KOHLER_OK or KOHLER_E_ARG. */
+int kohler_server_stats(kohler_server *srv, kohler_server_counters *out);
 
 #ifdef __cplusplus
 }

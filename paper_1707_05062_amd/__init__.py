@@ -17,9 +17,11 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _lib
-from ._lib import E_ARG, E_BUSY, E_CAPACITY, E_DEVICE, E_NOMEM, E_RANGE, OK, Plan  # noqa: F401
+from ._lib import (E_ARG, E_BUSY, E_CANCELED, E_CAPACITY, E_DEVICE, E_NOMEM, E_RANGE, OK,  # noqa: F401
+                   Plan, RequestInfo, ServerConfig, ServerCounters)
 
-__all__ = ["Context", "CurveResult", "KohlerError", "Plan", "curve", "default_context", "strerror"]
+__all__ = ["Context", "CurveResult", "KohlerError", "Plan", "Server", "curve", "default_context",
+           "strerror"]
 
 FORM_AUTO, FORM_BAND, FORM_MARG = 0, 1, 2
 
@@ -106,8 +108,8 @@ class Context:
 
     # -- plans -------------------------------------------------------------------------------
     def set_plan(self, dtype: int, M: int, nbhd: int, form: int = FORM_AUTO, band: int = 0,
-                 block: int = 512, grid: int = 0, px_per_lane: int = 4):
-        pl = Plan(form, band, block, grid, px_per_lane)
+                 block: int = 512, grid: int = 0, px_per_lane: int = 4, replicas: int = 0):
+        pl = Plan(form, band, block, grid, px_per_lane, replicas)
         st = self._lib.kohler_set_plan(self._h, dtype, M, nbhd, ctypes.byref(pl))
         if st != OK:
             raise KohlerError(st, "kohler_set_plan")
@@ -118,6 +120,31 @@ class Context:
         if st != OK:
             raise KohlerError(st, "kohler_get_plan")
         return pl.as_dict()
+
+    def autotune(self, imgs, M: int, nbhd: int = 4, reps: int = 5) -> tuple[dict, float]:
+        """Run the library's autotuner on device images (one image tunes the single-image launch,
+        several the batched one); the chosen plan is stored in this context. Returns (plan, us)."""
+        torch = _torch()
+        imgs = list(imgs)
+        n = len(imgs)
+        ptrs = (ctypes.c_void_p * n)()
+        Hs, Ws, Ps = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        code = None
+        for i, im in enumerate(imgs):
+            if not isinstance(im, torch.Tensor) or not im.is_cuda:
+                raise ValueError("autotune takes device tensors")
+            p, c, H, W, pitch, _ = _image_args(im)
+            if code is not None and c != code:
+                raise TypeError("all images must share one dtype")
+            code = c
+            ptrs[i], Hs[i], Ws[i], Ps[i] = p, H, W, pitch
+        best = Plan()
+        us = ctypes.c_double(0.0)
+        st = self._lib.kohler_autotune(self._h, n, ptrs, Hs, Ws, Ps, code, M, nbhd, reps,
+                                       ctypes.byref(best), ctypes.byref(us))
+        if st != OK:
+            raise KohlerError(st, "kohler_autotune")
+        return best.as_dict(), float(us.value)
 
     # -- synchronous -------------------------------------------------------------------------
     def curve(self, img, M: int, nbhd: int = 4, capacity: int | None = None,
@@ -211,6 +238,94 @@ class Context:
         if st != OK:
             raise KohlerError(st, "kohler_curve_batch")
         return out
+
+
+class Server:
+    """A serving loop on a context's device (kohler_server_*): submit images as they arrive,
+    collect results by ticket. See include/kohler.h for admission and batching."""
+
+    def __init__(self, ctx: Context, dtype: int = _lib.U8, M: int = 256, nbhd: int = 4,
+                 slots: int = 16, lanes: int = 2, max_batch: int = 16, queue_capacity: int = 4096,
+                 thr_capacity: int | None = None, use_graphs: bool = True,
+                 hbm_budget_bytes: int = 1 << 30):
+        self._lib = _lib.load()
+        self.ctx = ctx  # the context must outlive the server
+        self.M = int(M)
+        self.thr_capacity = self.M if thr_capacity is None else int(thr_capacity)
+        self.dtype = int(dtype)
+        cfg = ServerConfig(int(dtype), int(M), int(nbhd), int(slots), int(lanes), int(max_batch),
+                           int(queue_capacity), self.thr_capacity, 1 if use_graphs else 0, 0,
+                           int(hbm_budget_bytes))
+        self._h = ctypes.c_void_p()
+        st = self._lib.kohler_server_create(ctx._h, ctypes.byref(cfg), ctypes.byref(self._h))
+        if st != OK:
+            raise KohlerError(st, "kohler_server_create")
+        self._keep: dict[int, object] = {}
+
+    def close(self):
+        if self._h:
+            self._lib.kohler_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, img) -> int:
+        """Queue one image (host array, pinned tensor or device tensor); returns its ticket.
+        Raises KohlerError(E_BUSY) when admission is refused."""
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        if code != self.dtype:
+            raise TypeError("image dtype does not match the server")
+        t = ctypes.c_uint64(0)
+        st = self._lib.kohler_server_submit(self._h, ctypes.c_void_p(ptr), H, W, pitch, ctypes.byref(t))
+        if st != OK:
+            raise KohlerError(st, "kohler_server_submit")
+        self._keep[t.value] = keep  # the image must stay alive until the request completes
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        st = self._lib.kohler_server_poll(self._h, ticket)
+        if st < 0:
+            raise KohlerError(st, "kohler_server_poll")
+        return st == 1
+
+    def wait(self, ticket: int) -> tuple[CurveResult, dict]:
+        """Block until the request is done; returns its CurveResult and its info (status,
+        n_thresholds, t0, batch, graph, t_submit_ns, t_launch_ns, t_done_ns)."""
+        M, cap = self.M, self.thr_capacity
+        s = np.zeros(M, np.int64)
+        k = np.zeros(M, np.int64)
+        c = np.zeros(M, np.float64)
+        thr = np.zeros(max(cap, 1), np.int32)
+        info = RequestInfo()
+        st = self._lib.kohler_server_wait(self._h, ticket, s.ctypes.data, k.ctypes.data, c.ctypes.data,
+                                          thr.ctypes.data, cap, ctypes.byref(info))
+        self._keep.pop(ticket, None)
+        if st == E_ARG:
+            raise KohlerError(st, "kohler_server_wait")
+        n = int(info.n_thresholds)
+        return CurveResult(s, k, c, thr[: max(0, min(n, cap))].copy(), int(info.t0), n, st), info.as_dict()
+
+    def cancel(self, ticket: int) -> bool:
+        """True if the request was still queued and is now cancelled."""
+        st = self._lib.kohler_server_cancel(self._h, ticket)
+        if st == E_ARG:
+            raise KohlerError(st, "kohler_server_cancel")
+        return st == OK
+
+    def pause(self, paused: bool = True):
+        self._lib.kohler_server_pause(self._h, 1 if paused else 0)
+
+    def stats(self) -> dict:
+        out = ServerCounters()
+        st = self._lib.kohler_server_stats(self._h, ctypes.byref(out))
+        if st != OK:
+            raise KohlerError(st, "kohler_server_stats")
+        return out.as_dict()
 
 
 _default: dict[int, Context] = {}

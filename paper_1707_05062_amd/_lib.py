@@ -7,23 +7,50 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkohler.so")
 
-OK, E_ARG, E_RANGE, E_CAPACITY, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_RANGE, E_CAPACITY, E_NOMEM, E_DEVICE, E_BUSY, E_CANCELED = 0, -1, -2, -3, -4, -5, -6, -7
 U8, U16 = 1, 2
 MAX_M_U16 = 10200
 
 # every symbol include/kohler.h declares
 EXPORTS = (
     "kohler_create", "kohler_destroy", "kohler_strerror", "kohler_curve", "kohler_curve_async",
-    "kohler_curve_batch", "kohler_set_plan", "kohler_get_plan",
+    "kohler_curve_batch", "kohler_set_plan", "kohler_get_plan", "kohler_autotune",
+    "kohler_server_create", "kohler_server_destroy", "kohler_server_submit", "kohler_server_poll",
+    "kohler_server_wait", "kohler_server_cancel", "kohler_server_pause", "kohler_server_stats",
 )
 
 
-class Plan(ctypes.Structure):
-    _fields_ = [("form", ctypes.c_int32), ("band", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("grid", ctypes.c_int32), ("px_per_lane", ctypes.c_int32)]
-
+class _Struct(ctypes.Structure):
     def as_dict(self) -> dict:
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "pad"}
+
+
+class Plan(_Struct):
+    _fields_ = [("form", ctypes.c_int32), ("band", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("px_per_lane", ctypes.c_int32),
+                ("replicas", ctypes.c_int32)]
+
+
+class ServerConfig(_Struct):
+    _fields_ = [("dtype", ctypes.c_int32), ("M", ctypes.c_int32), ("nbhd", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("thr_capacity", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class RequestInfo(_Struct):
+    _fields_ = [("status", ctypes.c_int32), ("n_thresholds", ctypes.c_int32), ("t0", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("graph", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("t_submit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class ServerCounters(_Struct):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "completed", "refused", "cancelled", "launches", "graph_launches",
+        "batched_launches", "graphs_built", "max_batch_seen", "peak_inflight", "arena_bytes",
+        "arena_peak_bytes", "slot_state_bytes")]
 
 
 _lib = None
@@ -61,6 +88,26 @@ def load(path: str = LIB_PATH):
     lib.kohler_set_plan.restype = ctypes.c_int
     lib.kohler_get_plan.argtypes = [vp, ctypes.c_int, i64, i64, i32, i32, ctypes.POINTER(Plan)]
     lib.kohler_get_plan.restype = ctypes.c_int
+    lib.kohler_autotune.argtypes = [vp, i32, ctypes.POINTER(vp), i64p, i64p, i64p, ctypes.c_int, i32,
+                                    i32, i32, ctypes.POINTER(Plan), f64p]
+    lib.kohler_autotune.restype = ctypes.c_int
+    u64 = ctypes.c_uint64
+    lib.kohler_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.kohler_server_create.restype = ctypes.c_int
+    lib.kohler_server_destroy.argtypes = [vp]
+    lib.kohler_server_destroy.restype = None
+    lib.kohler_server_submit.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(u64)]
+    lib.kohler_server_submit.restype = ctypes.c_int
+    lib.kohler_server_poll.argtypes = [vp, u64]
+    lib.kohler_server_poll.restype = ctypes.c_int
+    lib.kohler_server_wait.argtypes = [vp, u64, vp, vp, vp, vp, i32, ctypes.POINTER(RequestInfo)]
+    lib.kohler_server_wait.restype = ctypes.c_int
+    lib.kohler_server_cancel.argtypes = [vp, u64]
+    lib.kohler_server_cancel.restype = ctypes.c_int
+    lib.kohler_server_pause.argtypes = [vp, i32]
+    lib.kohler_server_pause.restype = ctypes.c_int
+    lib.kohler_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
+    lib.kohler_server_stats.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
     return lib

@@ -14,8 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libkohler.so")
 
-SOURCES = ["kohler_kernels.hip", "kohler_api.cpp"]
-HEADERS = ["kohler_impl.h"]
+SOURCES = ["kohler_kernels.hip", "kohler_api.cpp", "kohler_server.cpp"]
+HEADERS = ["kohler_impl.h", "kohler_host.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

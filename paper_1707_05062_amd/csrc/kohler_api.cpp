@@ -1,5 +1,6 @@
-// C-ABI layer of the Köhler contrast-curve library: contexts, argument checks, launch plans and the
-// single-image, asynchronous and batched entry points declared in include/kohler.h.
+// C-ABI layer of the Köhler contrast-curve library: contexts, argument checks, launch plans, the
+// single-image, asynchronous and batched entry points and the autotuner declared in
+// include/kohler.h. The serving loop is in kohler_server.cpp.
 
 #include <hip/hip_runtime.h>
 
@@ -13,51 +14,12 @@
 #include <vector>
 
 #include "kohler.h"
+#include "kohler_host.h"
 #include "kohler_impl.h"
 
 using namespace kohler;
 
-struct kohler_ctx {
-    int device = 0;
-    int num_cus = 256;
-    hipStream_t stream = nullptr;
-
-    // single-image scratch (largest M), zero between calls
-    int64_t *acc1 = nullptr;
-    unsigned long long *done1 = nullptr;
-    uint32_t *rflag1 = nullptr;
-
-    // batch scratch, grown to the largest (n, M) seen
-    size_t batch_acc_words = 0;
-    int32_t batch_n = 0;
-    int64_t *accb = nullptr;
-    unsigned long long *doneb = nullptr;
-    uint32_t *rflagb = nullptr;
-    KImage *d_table = nullptr;
-    KImage *h_table = nullptr;  // pinned
-    int32_t table_cap = 0;
-
-    // synchronous entry point: device copy of a host image, device outputs, pinned host outputs
-    void *d_img = nullptr;
-    size_t d_img_bytes = 0;
-    int64_t *d_out_sc = nullptr;  // sum[M], count[M]
-    double *d_out_C = nullptr;
-    int32_t *d_out_i = nullptr;   // n_thr, t0, status
-    int32_t *d_thr = nullptr;
-    int32_t d_thr_cap = 0;
-    int64_t *h_out_sc = nullptr;
-    double *h_out_C = nullptr;
-    int32_t *h_out_i = nullptr;
-    int32_t *h_thr = nullptr;
-    int32_t h_thr_cap = 0;
-
-    std::map<std::tuple<int, int, int>, kohler_plan> plans;
-    std::mutex mu;
-};
-
-namespace {
-
-constexpr int kMaxM = std::max(kMaxMBand, kMaxMMarg);
+namespace kohler {
 
 int pick_status(hipError_t e) {
     if (e == hipSuccess) return KOHLER_OK;
@@ -83,6 +45,7 @@ bool valid_plan(const kohler_plan &pl, int dtype, int32_t M) {
     if (pl.form == FORM_MARG && M > kMaxMMarg) return false;
     if (pl.block != 256 && pl.block != 512) return false;
     if (pl.grid < 0 || pl.grid > 65535) return false;
+    if (pl.replicas < 0 || pl.replicas > kMaxReplicas) return false;
     if (dtype == KOHLER_U8 && pl.px_per_lane != 4 && pl.px_per_lane != 8) return false;
     if (dtype == KOHLER_U16 && pl.px_per_lane != 4) return false;
     return true;
@@ -95,6 +58,7 @@ kohler_plan default_plan(int dtype, int32_t M) {
     pl.block = 512;
     pl.grid = 0;
     pl.px_per_lane = 4;
+    pl.replicas = 0;
     (void)dtype;
     return pl;
 }
@@ -108,12 +72,14 @@ kohler_plan resolve_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, in
         pl = (it != ctx->plans.end()) ? it->second : default_plan(dtype, M);
     }
     if (pl.form == FORM_BAND && M > kMaxMBand) pl = default_plan(dtype, M);
+    if (pl.replicas == 0) pl.replicas = -1;  // filled in below, once the grid is known
     if (pl.grid == 0) {
         const int per_cu = blocks_per_cu(dtype, nbhd, pl.form, pl.px_per_lane, M, pl.band, pl.block);
         const int64_t waves = pl.block / 64;
         const int64_t want = (total_units + waves * 4 - 1) / (waves * 4);  // >= 4 rows per wave
         pl.grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * per_cu));
     }
+    if (pl.replicas < 0) pl.replicas = replicas_for(pl.grid);
     return pl;
 }
 
@@ -161,6 +127,10 @@ int grow_device(T **p, size_t &have, size_t want, bool zero) {
     return KOHLER_OK;
 }
 
+}  // namespace kohler
+
+namespace {
+
 int launch(kohler_ctx *ctx, const KParams &base, int dtype, int32_t nbhd, const kohler_plan &pl,
            hipStream_t stream) {
     KParams p = base;
@@ -184,6 +154,7 @@ const char *kohler_strerror(int status) {
         case KOHLER_E_NOMEM: return "out of memory";
         case KOHLER_E_DEVICE: return "HIP runtime error";
         case KOHLER_E_BUSY: return "admission refused";
+        case KOHLER_E_CANCELED: return "request cancelled";
         default: return "unknown status";
     }
 }
@@ -292,13 +263,17 @@ int kohler_curve_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H,
     p.M = M;
     p.cap = thr_capacity;
     p.packed_acc = packable(H, W, nbhd) ? 1 : 0;
-    p.nrep = replicas_for(pl.grid);
+    p.nrep = pl.replicas;
     p.rep_stride = replica_stride(M);
+    p.acc_stride = (int64_t)p.nrep * p.rep_stride;
     p.total_units = p.img0.nunits;
     p.acc = ctx->acc1;
     p.done = ctx->done1;
     p.rflag = ctx->rflag1;
     p.dyn = 1;
+    p.ostride = M;
+    p.istride = 1;
+    p.thr_stride = thr_capacity;
     p.sum = d_sum;
     p.count = d_count;
     p.C = d_C;
@@ -390,7 +365,7 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
     pl = resolve_plan(ctx, dtype, M, nbhd, total_units);
     // per-image scratch (replicas limited to keep it under 64 MiB) and the descriptor table
     const int64_t rstride = replica_stride(M);
-    int nrep = replicas_for(pl.grid);
+    int nrep = pl.replicas;
     while (nrep > 1 && (size_t)n * nrep * rstride > ((size_t)8 << 20)) nrep /= 2;
     const size_t acc_words = (size_t)n * nrep * (size_t)rstride;
     if (acc_words > ctx->batch_acc_words) {
@@ -426,6 +401,7 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
     int64_t ustart = 0;
     for (int32_t i = 0; i < n; ++i) {
         ctx->h_table[i] = describe(d_imgs[i], dtype, H[i], W[i], pitch[i], pl.px_per_lane, ustart);
+        ctx->h_table[i].out = i;
         ustart += ctx->h_table[i].nunits;
     }
     e = hipMemcpyAsync(ctx->d_table, ctx->h_table, sizeof(KImage) * n, hipMemcpyHostToDevice, stream);
@@ -442,7 +418,11 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
         if (!packable(H[i], W[i], nbhd)) p.packed_acc = 0;
     p.nrep = nrep;
     p.rep_stride = rstride;
+    p.acc_stride = (int64_t)nrep * rstride;
     p.total_units = ustart;
+    p.ostride = M;
+    p.istride = 1;
+    p.thr_stride = thr_capacity;
     p.acc = ctx->accb;
     p.done = ctx->doneb;
     p.rflag = ctx->rflagb;
@@ -454,6 +434,163 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
     p.t0 = d_t0;
     p.status = d_status;
     return launch(ctx, p, dtype, nbhd, pl, stream);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Autotuner: coordinate descent over the plan knobs, timing each candidate on the caller's workload.
+
+int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const int64_t *H,
+                    const int64_t *W, const int64_t *pitch, int dtype, int32_t M, int32_t nbhd,
+                    int32_t reps, kohler_plan *best, double *best_us) {
+    if (!ctx || n < 1 || !d_imgs || !H || !W || !pitch || !best || reps < 0 || reps > 1000) return KOHLER_E_ARG;
+    for (int32_t i = 0; i < n; ++i)
+        if (!d_imgs[i] || !valid_shape(dtype, H[i], W[i], pitch[i], M, nbhd)) return KOHLER_E_ARG;
+    if (reps == 0) reps = 5;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return pick_status(e);
+
+    const auto key = std::make_tuple(dtype, (int)M, (int)nbhd);
+    bool had_plan = false;
+    kohler_plan saved{};
+    {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        auto it = ctx->plans.find(key);
+        if (it != ctx->plans.end()) {
+            had_plan = true;
+            saved = it->second;
+        }
+    }
+    auto restore = [&]() {
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (had_plan) ctx->plans[key] = saved;
+        else ctx->plans.erase(key);
+    };
+
+    // trial outputs: image-major arrays as kohler_curve_batch writes them
+    const int32_t cap = M / 2 + 1;
+    const size_t words = (size_t)n * (3 * (size_t)M + 2 + (size_t)(cap + 1) / 2 + 2);
+    int64_t *buf = nullptr;
+    if ((e = hipMalloc(&buf, words * sizeof(int64_t))) != hipSuccess) return pick_status(e);
+    int64_t *d_sum = buf, *d_count = buf + (size_t)n * M;
+    double *d_C = reinterpret_cast<double *>(buf + (size_t)2 * n * M);
+    int32_t *d_int = reinterpret_cast<int32_t *>(buf + (size_t)3 * n * M);
+    int32_t *d_n = d_int, *d_t0 = d_int + n, *d_st = d_int + 2 * n, *d_thr = d_int + 4 * n;
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    for (auto &x : ev)
+        if (e == hipSuccess) e = hipEventCreate(&x);
+
+    auto run_once = [&]() -> int {
+        if (n == 1)
+            return kohler_curve_async(ctx, d_imgs[0], dtype, H[0], W[0], pitch[0], M, nbhd, d_sum, d_count,
+                                      d_C, d_thr, cap, d_n, d_t0, d_st, ctx->stream);
+        return kohler_curve_batch(ctx, n, d_imgs, H, W, pitch, dtype, M, nbhd, d_sum, d_count, d_C, d_thr,
+                                  cap, d_n, d_t0, d_st, ctx->stream);
+    };
+    // median launch time of a plan in microseconds, or a negative status
+    std::map<std::tuple<int, int, int, int, int, int>, double> seen;
+    auto time_plan = [&](const kohler_plan &pl, double *us) -> int {
+        const auto k = std::make_tuple(pl.form, pl.band, pl.block, pl.grid, pl.px_per_lane, pl.replicas);
+        auto it = seen.find(k);
+        if (it != seen.end()) {
+            *us = it->second;
+            return KOHLER_OK;
+        }
+        int st = kohler_set_plan(ctx, dtype, M, nbhd, &pl);
+        if (st != KOHLER_OK) return st;
+        for (int w = 0; w < 2 && st == KOHLER_OK; ++w) st = run_once();
+        for (int r = 0; r < reps && st == KOHLER_OK; ++r) {
+            if ((e = hipEventRecord(ev[2 * r], ctx->stream)) != hipSuccess) return pick_status(e);
+            st = run_once();
+            if ((e = hipEventRecord(ev[2 * r + 1], ctx->stream)) != hipSuccess) return pick_status(e);
+        }
+        if (st != KOHLER_OK) return st;
+        if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return pick_status(e);
+        std::vector<float> ms((size_t)reps);
+        for (int r = 0; r < reps; ++r)
+            if ((e = hipEventElapsedTime(&ms[r], ev[2 * r], ev[2 * r + 1])) != hipSuccess) return pick_status(e);
+        std::sort(ms.begin(), ms.end());
+        *us = 1000.0 * ms[(size_t)reps / 2];
+        seen[k] = *us;
+        return KOHLER_OK;
+    };
+
+    // candidate values of each knob
+    std::vector<std::pair<int, int>> shapes;  // (form, band)
+    if (M <= kMaxMBand)
+        for (int b : {8, 16, 24, 32, 48, 64})
+            if (b <= std::max(1, M - 1)) shapes.emplace_back(FORM_BAND, b);
+    if (M <= kMaxMMarg) shapes.emplace_back(FORM_MARG, 1);
+    std::vector<int> ppls = dtype == KOHLER_U8 ? std::vector<int>{4, 8} : std::vector<int>{4};
+    const std::vector<int> blocks = {256, 512};
+    const std::vector<int> reps_knob = {0, 1, 2, 4, 8, 16};
+
+    kohler_plan cur = default_plan(dtype, M);
+    double cur_us = 0.0;
+    int st = (e == hipSuccess) ? time_plan(cur, &cur_us) : pick_status(e);
+    for (int pass = 0; pass < 2 && st == KOHLER_OK; ++pass) {
+        auto try_plan = [&](kohler_plan pl) {
+            if (st != KOHLER_OK) return;
+            double us = 0.0;
+            const int r = time_plan(pl, &us);
+            if (r == KOHLER_E_ARG) return;  // not a valid plan for this family (e.g. LDS too large)
+            if (r != KOHLER_OK) {
+                st = r;
+                return;
+            }
+            if (us < cur_us) {
+                cur = pl;
+                cur_us = us;
+            }
+        };
+        const kohler_plan base_shape = cur;
+        for (auto fb : shapes) {
+            kohler_plan pl = base_shape;
+            pl.form = fb.first;
+            pl.band = fb.second;
+            try_plan(pl);
+        }
+        const kohler_plan base_ppl = cur;
+        for (int v : ppls) {
+            kohler_plan pl = base_ppl;
+            pl.px_per_lane = v;
+            try_plan(pl);
+        }
+        const kohler_plan base_block = cur;
+        for (int v : blocks) {
+            kohler_plan pl = base_block;
+            pl.block = v;
+            try_plan(pl);
+        }
+        // grid: automatic, or 1..4 workgroups per compute unit within the occupancy limit
+        const kohler_plan base_grid = cur;
+        const int per_cu = blocks_per_cu(dtype, nbhd, cur.form, cur.px_per_lane, M, cur.band, cur.block);
+        for (int v = 0; v <= std::min(4, per_cu); ++v) {
+            kohler_plan pl = base_grid;
+            pl.grid = v * ctx->num_cus;
+            try_plan(pl);
+        }
+        const kohler_plan base_rep = cur;
+        for (int v : reps_knob) {
+            kohler_plan pl = base_rep;
+            pl.replicas = v;
+            try_plan(pl);
+        }
+    }
+    for (auto &x : ev)
+        if (x) (void)hipEventDestroy(x);
+    (void)hipFree(buf);
+    if (st != KOHLER_OK) {
+        restore();
+        return st;
+    }
+    st = kohler_set_plan(ctx, dtype, M, nbhd, &cur);
+    if (st != KOHLER_OK) {
+        restore();
+        return st;
+    }
+    *best = cur;
+    if (best_us) *best_us = cur_us;
+    return KOHLER_OK;
 }
 
 }  // extern "C"

@@ -17,10 +17,16 @@ struct KImage {
     int64_t nunits;
     int32_t nstrips;
     int32_t vec_ok;       // 1 when base and pitch allow aligned vector loads of px_per_lane pixels
+    int32_t out;          // index of this image's outputs and scratch (see KParams)
+    int32_t pad;
 };
 
-// Kernel arguments. Outputs and scratch are image-major: image i uses acc + i*2*M, sum + i*M,
-// thr + i*cap, n_thr + i, and so on.
+// Kernel arguments. Outputs and scratch are indexed by the image's `out` field o: the image uses the
+// accumulators at acc + o*acc_stride, done[o] and rflag[o], and writes sum + o*ostride,
+// count + o*ostride, C + o*ostride (M values each), thr + o*istride (cap values), n_thr + o*istride,
+// t0 + o*istride and status + o*istride. A batch call numbers its images 0..n-1 with ostride = M,
+// istride = 1 for the scalars and cap for thr (thr_stride); the server gives each image the index
+// of the slot that holds it and lays a slot's outputs out as one record.
 struct KParams {
     const KImage *imgs;   // device table, used when n > 1
     KImage img0;          // inline descriptor, used when n == 1
@@ -28,14 +34,18 @@ struct KParams {
     int32_t packed_acc;   // 1: acc holds E * 2^32 + D1 in one word per level (images small enough)
     int32_t nrep;         // accumulator replicas per image; workgroup b adds into replica b % nrep
     int64_t rep_stride;   // int64 words between replicas (>= 2M)
+    int64_t acc_stride;   // int64 words between the accumulators of two output indices (>= nrep*rep_stride)
     int64_t total_units;
-    int64_t *acc;         // [n][nrep][rep_stride] int64: per replica, the first-difference array
-                          // of #B(t) then the second-difference array of the contrast sums (or
-                          // both packed in the first M words); all zero between launches
-    unsigned long long *done;  // [n] units completed in the current launch; zero between launches
+    int64_t *acc;         // per output index, nrep replicas of rep_stride int64 words: the
+                          // first-difference array of #B(t) then the second-difference array of the
+                          // contrast sums (or both packed in the first M words); zero between launches
+    unsigned long long *done;  // per output index: units completed in the current launch; zero between launches
     int32_t dyn;          // 1: one image, chunks dealt round-robin to the workgroups
     int32_t pad1;
-    uint32_t *rflag;      // [n] set when a pixel >= M was seen; zero between launches
+    uint32_t *rflag;      // per output index: set when a pixel >= M was seen; zero between launches
+    int64_t ostride;      // elements between the sum/count/C arrays of two output indices
+    int64_t istride;      // elements between the n_thr/t0/status entries of two output indices
+    int64_t thr_stride;   // elements between the thr arrays of two output indices
     int64_t *sum;
     int64_t *count;
     double *C;
@@ -90,6 +100,11 @@ inline size_t lds_bytes(int form, int M, int band, int block) {
 
 // Workgroups of this launch family that fit on one compute unit at once.
 int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block);
+
+// The kernel instance of a launch family and the dynamic LDS bytes it needs (for graph kernel
+// nodes); allows the kernel to use that much LDS.
+hipError_t curve_kernel_for(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block,
+                            const void **func, size_t *lds);
 
 // Launch the curve kernel. Returns hipSuccess or the launch error.
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,

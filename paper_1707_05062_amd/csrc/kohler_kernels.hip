@@ -539,7 +539,8 @@ __device__ __forceinline__ uint64_t merge_marg(const KParams &p, lds_u32 *lds, i
 }
 
 // ------------------------------------------------------------------------------------------------
-// finalize: prefix sums, C, local maxima and t0 for image i (run by one workgroup)
+// finalize: prefix sums, C, local maxima and t0 for the image with output index i (run by one
+// workgroup)
 //
 // LDS use (the histogram tables are dead by now): two int64 arrays of blockDim + 1 entries holding
 // the current chunk's (sum, count) shifted by one, so each thread sees its left neighbour, then one
@@ -547,12 +548,12 @@ __device__ __forceinline__ uint64_t merge_marg(const KParams &p, lds_u32 *lds, i
 
 __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, LdsScratch &bs) {
     const int M = p.M, tid = threadIdx.x, nt = blockDim.x;
-    unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * p.nrep * p.rep_stride);
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * p.acc_stride);
     const int R = p.nrep;
     const int64_t RS = p.rep_stride;
-    int64_t *osum = p.sum + (int64_t)i * M;
-    int64_t *ocnt = p.count + (int64_t)i * M;
-    double *oC = p.C + (int64_t)i * M;
+    int64_t *osum = p.sum + (int64_t)i * p.ostride;
+    int64_t *ocnt = p.count + (int64_t)i * p.ostride;
+    double *oC = p.C + (int64_t)i * p.ostride;
     KOHLER_LDS int64_t *csum = reinterpret_cast<KOHLER_LDS int64_t *>(lds);
     KOHLER_LDS int64_t *ccnt = csum + (nt + 1);
     KOHLER_LDS uint8_t *flags = reinterpret_cast<KOHLER_LDS uint8_t *>(ccnt + (nt + 1));
@@ -635,7 +636,7 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
     __syncthreads();
 
     // local maxima: a run start (t == 0 or a rise) with positive C whose run ends in a fall or at M
-    int32_t *othr = p.thr + (int64_t)i * p.cap;
+    int32_t *othr = p.thr + (int64_t)i * p.thr_stride;
     int64_t found = 0;
     for (int b = 0; b < M; b += nt) {
         const int t = b + tid;
@@ -691,9 +692,9 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
         if (t0 >= 0 && cmp_curve(s0, k0, 0, 1) <= 0) t0 = -1;
         __hip_atomic_store(gptr(p.rflag + i), 0u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
         store_shared(p.done + i, 0);
-        p.n_thr[i] = (int32_t)found;
-        p.t0[i] = t0;
-        p.status[i] = rf ? ST_RANGE : (found > p.cap ? ST_CAPACITY : ST_OK);
+        p.n_thr[(int64_t)i * p.istride] = (int32_t)found;
+        p.t0[(int64_t)i * p.istride] = t0;
+        p.status[(int64_t)i * p.istride] = rf ? ST_RANGE : (found > p.cap ? ST_CAPACITY : ST_OK);
     }
     // stores last, after every barrier, so that no barrier waits for them
     if (one_chunk && tid < M) {
@@ -727,6 +728,11 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// Output index of image i (used only on the error path, from one thread).
+__device__ __forceinline__ int image_desc_out(const KParams &p, int i) {
+    return p.n == 1 ? p.img0.out : gptr(p.imgs)[i].out;
+}
+
 // The descriptor of image i, with every field wave-uniform (scalar registers).
 __device__ __forceinline__ KImage image_desc(const KParams &p, int i) {
     KImage im = p.img0;
@@ -740,6 +746,7 @@ __device__ __forceinline__ KImage image_desc(const KParams &p, int i) {
         im.nunits = q->nunits;
         im.nstrips = q->nstrips;
         im.vec_ok = q->vec_ok;
+        im.out = q->out;
     }
     im.ptr = (const void *)uniform64((int64_t)im.ptr);
     im.H = uniform64(im.H);
@@ -749,6 +756,7 @@ __device__ __forceinline__ KImage image_desc(const KParams &p, int i) {
     im.nunits = uniform64(im.nunits);
     im.nstrips = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)im.nstrips);
     im.vec_ok = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)im.vec_ok);
+    im.out = (int32_t)__builtin_amdgcn_readfirstlane((uint32_t)im.out);
     return im;
 }
 
@@ -762,7 +770,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
     if ((uint32_t)(size_t)lds != 0u) {
         // the LDS layout assumption behind lds_at() does not hold: report, compute nothing
         if (blockIdx.x == 0 && threadIdx.x == 0)
-            for (int i = 0; i < p.n; ++i) p.status[i] = ST_LAYOUT;
+            for (int i = 0; i < p.n; ++i) p.status[(int64_t)image_desc_out(p, i) * p.istride] = ST_LAYOUT;
         return;
     }
     const int G = gridDim.x;
@@ -799,9 +807,10 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         return vmax;
     };
 
-    // After the pair work of `units` units of image i: range flag, merge into the image's
+    // After the pair work of `units` units of image im: range flag, merge into the image's
     // accumulators, ticket, and the finalize step when this workgroup completed the image.
-    auto flush = [&](int i, const KImage &im, uint32_t vmax, int64_t units) {
+    auto flush = [&](const KImage &im, uint32_t vmax, int64_t units) {
+        const int i = im.out;
         uint64_t sink = 0;
         if constexpr (CLAMP) {
             vmax = wave_max(vmax);
@@ -810,7 +819,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         }
         __syncthreads();
         if (units == 0) return;  // uniform: nothing to add, and no ticket to take
-        int64_t *acc_g = p.acc + ((int64_t)i * p.nrep + (int64_t)(blockIdx.x % (uint32_t)p.nrep)) * p.rep_stride;
+        int64_t *acc_g = p.acc + (int64_t)i * p.acc_stride + (int64_t)(blockIdx.x % (uint32_t)p.nrep) * p.rep_stride;
         if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
         else sink ^= merge_marg(p, lds, acc_g);
 
@@ -851,7 +860,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         // units of this workgroup: full chunks, less the short last chunk of the image if it is ours
         int64_t units = mine * kChunk;
         if (mine > 0 && (nchunks - 1) % G == g) units -= nchunks * kChunk - im.nunits;
-        flush(0, im, vmax, units);
+        flush(im, vmax, units);
         return;
     }
 
@@ -880,7 +889,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
                 wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
             }
         });
-        flush(i, im, vmax, nseg);
+        flush(im, vmax, nseg);
         u = seg_end;
     }
 }
@@ -910,6 +919,13 @@ hipError_t allow_large_lds(const void *kern) {
 }
 
 }  // namespace
+
+hipError_t curve_kernel_for(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block,
+                            const void **func, size_t *lds) {
+    *lds = lds_bytes(form, M, band, block);
+    *func = pick_kernel(dtype, nbhd, form, px_per_lane, M);
+    return allow_large_lds(*func);
+}
 
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,
                         int grid, hipStream_t stream) {
