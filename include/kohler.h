@@ -209,7 +209,10 @@ typedef struct kohler_request_info {
     int32_t batch;        /* requests in the launch that computed it */
     int32_t graph;        /* 1 if it ran as a graph replay */
     int32_t pad;
-    int64_t t_submit_ns, t_launch_ns, t_done_ns;  /* t_done: results in host memory, seen by the server */
+    int64_t t_submit_ns;  /* submit accepted the request */
+    int64_t t_launch_ns;  /* admitted: the scheduler started issuing its launch */
+    int64_t t_issued_ns;  /* every operation of its launch was enqueued on the lane */
+    int64_t t_done_ns;    /* results in host memory, seen by the server */
 } kohler_request_info;
 
 typedef struct kohler_server_counters {

@@ -43,7 +43,7 @@ class RequestInfo(_Struct):
     _fields_ = [("status", ctypes.c_int32), ("n_thresholds", ctypes.c_int32), ("t0", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("graph", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("t_submit_ns", ctypes.c_int64), ("t_launch_ns", ctypes.c_int64),
-                ("t_done_ns", ctypes.c_int64)]
+                ("t_issued_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64)]
 
 
 class ServerCounters(_Struct):

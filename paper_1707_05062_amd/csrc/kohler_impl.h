@@ -84,12 +84,14 @@ struct BlockScratch {
 // the gap and the low value (a 256-word stride would put every gap of one low value in one bank).
 constexpr int kRowStride = 257;
 
-// LDS bytes before the BlockScratch: the histogram tables, or the finalize step's arrays (two int64
-// arrays of block + 1 entries and one byte per grey level), whichever is larger; 16-byte aligned.
+// LDS bytes before the BlockScratch: the histogram tables, or the finalize step's arrays, whichever
+// is larger; 16-byte aligned. Finalize for M <= 256 keeps two int64 partial sums per wave and level
+// (256 levels); for larger M, two int64 arrays of block + 1 entries and one byte per grey level.
 __host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int block) {
     const size_t words = (form == FORM_BAND) ? ((size_t)band + 2) * kRowStride + 768 : 4 * (size_t)M;
     const size_t table = (words * 4 + 15) & ~(size_t)15;
-    const size_t fin = (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
+    const size_t fin = M <= 256 ? (size_t)(block / 64) * 2 * 256 * 8
+                                : (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
     return table > fin ? table : fin;
 }
 

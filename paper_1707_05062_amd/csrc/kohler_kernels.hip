@@ -539,6 +539,297 @@ __device__ __forceinline__ uint64_t merge_marg(const KParams &p, lds_u32 *lds, i
 }
 
 // ------------------------------------------------------------------------------------------------
+// Wave-wide primitives for the one-wave finalize (all 64 lanes active)
+
+// The int64 value of the lane selected by DPP control CTRL (rows outside ROW_MASK, and lanes whose
+// source is outside their row, read 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over the wave: shifts by 1, 2, 4 and 8 inside each row of 16 lanes, then row
+// 0's total into row 1 and row 2's into row 3, then the first 32 lanes' total into rows 2 and 3.
+__device__ __forceinline__ int64_t wave_iscan(int64_t v) {
+    uint64_t x = (uint64_t)v;
+    x += dpp64<0x111, 0xF>(x);  // row_shr:1
+    x += dpp64<0x112, 0xF>(x);  // row_shr:2
+    x += dpp64<0x114, 0xF>(x);  // row_shr:4
+    x += dpp64<0x118, 0xF>(x);  // row_shr:8
+    x += dpp64<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp64<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return (int64_t)x;
+}
+
+// Running maximum over the wave (same pattern; 0 is the identity for the unsigned values used).
+__device__ __forceinline__ uint64_t wave_imax(uint64_t x) {
+    x = max(x, dpp64<0x111, 0xF>(x));
+    x = max(x, dpp64<0x112, 0xF>(x));
+    x = max(x, dpp64<0x114, 0xF>(x));
+    x = max(x, dpp64<0x118, 0xF>(x));
+    x = max(x, dpp64<0x142, 0xA>(x));
+    x = max(x, dpp64<0x143, 0xC>(x));
+    return x;
+}
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Lane l receives lane l-1's value; lane 0 receives 0.
+__device__ __forceinline__ int64_t prev_lane64(int64_t x) {
+    const uint32_t lo = from_prev_lane((uint32_t)(uint64_t)x, 0u);
+    const uint32_t hi = from_prev_lane((uint32_t)((uint64_t)x >> 32), 0u);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Set lanes of `mask` below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// ------------------------------------------------------------------------------------------------
+// One-wave finalize for M <= 256: prefix sums, C, local maxima and t0 for the image with output
+// index i. Lane l owns the thresholds 4l .. 4l+3.
+//
+// Every wave of the workgroup first sums a share of the accumulator replicas (replicas w, w + nw, ...
+// for wave w) for all 256 levels into LDS and clears what it read; after one barrier wave 0 does the
+// rest alone, with DPP scans and ballots instead of barriers. The other waves return.
+//
+// Local maxima: a run of equal C values starting at t (t = 0, or C(t) > C(t-1)) with C(t) > 0 is a
+// local maximum when the first change of C after t is a fall, or there is none before M.
+// t0: the largest C is found on the doubles (the division rounds correctly, so it is monotone and
+// every t with the exact largest value has the largest double); a tie between several t is settled
+// by exact comparison of sum/count, keeping the smallest t.
+
+constexpr int kWaveT = 4;          // thresholds per lane
+constexpr int kWaveMaxM = 64 * kWaveT;
+
+__device__ __forceinline__ void finalize_wave(const KParams &p, int i, lds_u32 *lds) {
+    const int M = p.M, R = p.nrep, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t RS = p.rep_stride;
+    const bool packed = p.packed_acc != 0;
+    unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * p.acc_stride);
+    KOHLER_LDS int64_t *part = reinterpret_cast<KOHLER_LDS int64_t *>(lds);  // [nw][2][256]
+    const int tb = kWaveT * lane;
+
+    // 1. replica sums, a share per wave; every load is issued before any is used (replica indices
+    //    past R and levels past M re-read a valid word and are dropped), then the words are cleared
+    {
+        constexpr int kRepsPerWave = kMaxReplicas / 4;  // blockDim.x >= 256
+        // sum of this wave's replicas of the array starting at word `base` of each replica
+        auto gather = [&](int base, int64_t (&s)[kWaveT]) {
+            uint64_t v[kRepsPerWave][kWaveT];
+#pragma unroll
+            for (int k = 0; k < kRepsPerWave; ++k) {
+                const int r = min(w + k * nw, R - 1);
+#pragma unroll
+                for (int q = 0; q < kWaveT; ++q) v[k][q] = load_shared(acc + r * RS + base + (tb + q < M ? tb + q : 0));
+            }
+#pragma unroll
+            for (int q = 0; q < kWaveT; ++q) s[q] = 0;
+#pragma unroll
+            for (int k = 0; k < kRepsPerWave; ++k) {
+                const bool use = w + k * nw < R;
+#pragma unroll
+                for (int q = 0; q < kWaveT; ++q) s[q] += use ? (int64_t)v[k][q] : 0;
+            }
+        };
+        int64_t s0[kWaveT], s1[kWaveT] = {0, 0, 0, 0};
+        gather(0, s0);
+        if (!packed) gather(M, s1);  // images with 2^30 or more pairs only
+#pragma unroll
+        for (int k = 0; k < kRepsPerWave; ++k) {
+            const int r = w + k * nw;
+            if (r < R) {
+#pragma unroll
+                for (int q = 0; q < kWaveT; ++q) {
+                    if (tb + q < M) {
+                        store_shared(acc + r * RS + tb + q, 0);
+                        if (!packed) store_shared(acc + r * RS + M + tb + q, 0);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kWaveT; ++q) {
+            part[(2 * w) * kWaveMaxM + tb + q] = s0[q];
+            part[(2 * w + 1) * kWaveMaxM + tb + q] = s1[q];
+        }
+    }
+    __syncthreads();
+    if (w != 0) return;
+
+    uint32_t rf = 0;
+    if (lane == 0) rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
+
+    // 2. D1 and E of this lane's levels
+    int64_t d1[kWaveT], e[kWaveT];
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        int64_t a = 0, b = 0;
+        for (int v = 0; v < nw; ++v) {
+            a += part[(2 * v) * kWaveMaxM + tb + q];
+            b += part[(2 * v + 1) * kWaveMaxM + tb + q];
+        }
+        if (packed) {
+            // E * 2^32 + D1 summed as one word: |D1| < 2^31 because the image has < 2^30 pairs
+            d1[q] = (int64_t)(int32_t)(uint32_t)(uint64_t)a;
+            e[q] = (a - d1[q]) >> 32;
+        } else {
+            d1[q] = a;
+            e[q] = b;
+        }
+        if (tb + q >= M) d1[q] = e[q] = 0;
+    }
+
+    // 3. count = prefix of D1; with P0 = prefix of E and P1 = prefix of v*E, sum(t) = (t+1) P0 - P1
+    int64_t c0[kWaveT], c1[kWaveT], c2[kWaveT];
+    int64_t r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        r0 += d1[q];
+        r1 += e[q];
+        r2 += (int64_t)(tb + q) * e[q];
+        c0[q] = r0;
+        c1[q] = r1;
+        c2[q] = r2;
+    }
+    const int64_t x0 = wave_iscan(r0) - r0, x1 = wave_iscan(r1) - r1, x2 = wave_iscan(r2) - r2;
+    int64_t sm[kWaveT], cnt[kWaveT];
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        cnt[q] = x0 + c0[q];
+        sm[q] = (int64_t)(tb + q + 1) * (x1 + c1[q]) - (x2 + c2[q]);
+    }
+
+    // 4. relation of C(t) to C(t-1), positivity, and the masks over all levels
+    const int64_t ps = prev_lane64(sm[kWaveT - 1]), pk = prev_lane64(cnt[kWaveT - 1]);
+    int rel[kWaveT];
+    uint64_t NE[kWaveT], FA[kWaveT], ST[kWaveT];
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        const int t = tb + q;
+        const bool valid = t < M;
+        rel[q] = (t == 0 || !valid) ? 0 : cmp_curve(sm[q], cnt[q], q ? sm[q - 1] : ps, q ? cnt[q - 1] : pk);
+        NE[q] = __ballot(rel[q] != 0);
+        FA[q] = __ballot(rel[q] < 0);
+        ST[q] = __ballot(valid && sm[q] > 0 && (t == 0 || rel[q] > 0));
+    }
+    const uint64_t ne_any = NE[0] | NE[1] | NE[2] | NE[3];
+    const uint64_t later = lane == 63 ? 0ull : ne_any & (~0ull << (lane + 1));
+    // first change after this lane's levels: 1 = fall, 0 = rise, -1 = none before M
+    int next_fall = -1;
+    if (later) {
+        const int l2 = __builtin_ctzll(later);
+        const int q2 = ((NE[0] >> l2) & 1) ? 0 : ((NE[1] >> l2) & 1) ? 1 : ((NE[2] >> l2) & 1) ? 2 : 3;
+        next_fall = (int)((FA[q2] >> l2) & 1);
+    }
+    bool is_max[kWaveT];
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        int nf = next_fall;  // first change after level q: look inside the lane first
+#pragma unroll
+        for (int q2 = kWaveT - 1; q2 > q; --q2)
+            if (rel[q2] != 0) nf = rel[q2] < 0 ? 1 : 0;
+        is_max[q] = ((ST[q] >> lane) & 1) && nf != 0;
+    }
+
+    // 5. compaction of the maxima in ascending order
+    uint64_t MX[kWaveT];
+    uint32_t below = 0, found = 0;
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        MX[q] = __ballot(is_max[q]);
+        below += lanes_below(MX[q]);
+        found += (uint32_t)__builtin_popcountll(MX[q]);
+    }
+    int32_t *othr = p.thr + (int64_t)i * p.thr_stride;
+    uint32_t own = 0;
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        if (is_max[q]) {
+            const uint32_t pos = below + own;
+            if ((int64_t)pos < (int64_t)p.cap) othr[pos] = tb + q;
+            ++own;
+        }
+    }
+
+    // 6. C, and t0
+    double C[kWaveT];
+    uint64_t cb = 0;
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        C[q] = cnt[q] ? (double)sm[q] / (double)cnt[q] : 0.0;
+        if (tb + q < M) cb = max(cb, (uint64_t)__double_as_longlong(C[q]));  // C >= 0: bits order as values
+    }
+    const uint64_t cmax = readlane64(wave_imax(cb), 63);
+    int32_t t0 = -1;
+    if (cmax != 0) {
+        uint64_t CA[kWaveT];
+        uint32_t ncand = 0;
+#pragma unroll
+        for (int q = 0; q < kWaveT; ++q) {
+            CA[q] = __ballot(tb + q < M && (uint64_t)__double_as_longlong(C[q]) == cmax);
+            ncand += (uint32_t)__builtin_popcountll(CA[q]);
+        }
+        if (ncand == 1) {
+#pragma unroll
+            for (int q = 0; q < kWaveT; ++q)
+                if (CA[q]) t0 = kWaveT * __builtin_ctzll(CA[q]) + q;
+        } else {
+            // several levels share the largest double: compare them exactly, in ascending t
+            KOHLER_LDS int64_t *ts = part, *tk = part + kWaveMaxM;
+#pragma unroll
+            for (int q = 0; q < kWaveT; ++q) {
+                ts[tb + q] = sm[q];
+                tk[tb + q] = cnt[q];
+            }
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {
+                int64_t bs_ = 0, bk_ = 0;
+                for (int t = 0; t < M; ++t) {
+                    if (!((CA[t % kWaveT] >> (t / kWaveT)) & 1)) continue;
+                    if (t0 < 0 || cmp_curve(ts[t], tk[t], bs_, bk_) > 0) {
+                        t0 = t;
+                        bs_ = ts[t];
+                        bk_ = tk[t];
+                    }
+                }
+            }
+            t0 = __builtin_amdgcn_readfirstlane(t0);
+        }
+    }
+
+    // 7. outputs and counters for the next launch
+    int64_t *osum = p.sum + (int64_t)i * p.ostride;
+    int64_t *ocnt = p.count + (int64_t)i * p.ostride;
+    double *oC = p.C + (int64_t)i * p.ostride;
+#pragma unroll
+    for (int q = 0; q < kWaveT; ++q) {
+        if (tb + q < M) {
+            osum[tb + q] = sm[q];
+            ocnt[tb + q] = cnt[q];
+            oC[tb + q] = C[q];
+        }
+    }
+    if (lane == 0) {
+        __hip_atomic_store(gptr(p.rflag + i), 0u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
+        store_shared(p.done + i, 0);
+        p.n_thr[(int64_t)i * p.istride] = (int32_t)found;
+        p.t0[(int64_t)i * p.istride] = t0;
+        p.status[(int64_t)i * p.istride] = rf ? ST_RANGE : ((int64_t)found > (int64_t)p.cap ? ST_CAPACITY : ST_OK);
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // finalize: prefix sums, C, local maxima and t0 for the image with output index i (run by one
 // workgroup)
 //
@@ -833,17 +1124,28 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
             bs.last = (old + (unsigned long long)units == (unsigned long long)im.nunits) ? 1 : 0;
         }
         __syncthreads();
-        if (bs.last) finalize(p, i, lds, bs);
+        if (bs.last) {
+            if (p.M <= kWaveMaxM) finalize_wave(p, i, lds);
+            else finalize(p, i, lds, bs);
+        }
         __syncthreads();
     };
 
     if (p.dyn) {
-        // One image: chunks of kChunk units are dealt round-robin to the workgroups (chunk c to
-        // logical workgroup c mod G), so every workgroup samples the whole image and costly regions
-        // (many large-gap pairs) spread evenly; waves claim their workgroup's chunks in turn.
+        // One image: a chunk is kChunk consecutive rows of one strip. Chunks are numbered row-block
+        // major (chunk c covers strip c mod nstrips of row block c / nstrips), so neighbouring
+        // strips of the same rows get consecutive numbers, and they are dealt round-robin to the
+        // workgroups (chunk c to logical workgroup c mod G): every workgroup samples the whole image,
+        // costly regions (many large-gap pairs) spread evenly, and the next strip's first column,
+        // which a strip's rows also read, is fetched at about the same time by a workgroup on the
+        // same XCD (shared L2). Waves claim their workgroup's chunks in turn.
         const KImage im = image_desc(p, 0);
-        const int64_t nchunks = (im.nunits + kChunk - 1) / kChunk;
-        const int64_t mine = g < nchunks ? (nchunks - g + G - 1) / G : 0;  // chunks of this workgroup
+        const int64_t ns = im.nstrips;
+        const int64_t nblocks = (im.H + kChunk - 1) / kChunk;
+        const int64_t nchunks = nblocks * ns;
+        // number of chunks c < n with c = g (mod G)
+        auto upto = [&](int64_t n) -> int64_t { return n > g ? (n - g - 1) / G + 1 : 0; };
+        const int64_t mine = upto(nchunks);  // chunks of this workgroup
         clear_tables();
         auto claim = [&]() -> uint32_t {
             uint32_t k = 0;
@@ -853,13 +1155,16 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         };
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
             for (uint32_t j = claim(); j < mine; j = claim()) {
-                const int64_t ca = ((int64_t)g + (int64_t)j * G) * kChunk, cb = min(im.nunits, ca + kChunk);
+                const int64_t c = (int64_t)g + (int64_t)j * G;
+                const int64_t blk = c / ns, strip = c - blk * ns;
+                const int64_t ca = strip * im.H + blk * kChunk;  // strip-major unit numbers
+                const int64_t cb = strip * im.H + min(im.H, (blk + 1) * kChunk);
                 wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
             }
         });
-        // units of this workgroup: full chunks, less the short last chunk of the image if it is ours
-        int64_t units = mine * kChunk;
-        if (mine > 0 && (nchunks - 1) % G == g) units -= nchunks * kChunk - im.nunits;
+        // units of this workgroup: kChunk rows per chunk, less the short chunks of the last row block
+        const int64_t last_rows = im.H - (nblocks - 1) * kChunk;
+        const int64_t units = mine * kChunk - (upto(nchunks) - upto(nchunks - ns)) * (kChunk - last_rows);
         flush(im, vmax, units);
         return;
     }

@@ -104,7 +104,7 @@ struct Request {
     bool has_arena = false;
     size_t arena_off = 0;
     int32_t status = KOHLER_OK, n_thr = 0, t0 = -1, batch = 0, graph = 0;
-    int64_t t_submit = 0, t_launch = 0, t_done = 0;
+    int64_t t_submit = 0, t_launch = 0, t_issued = 0, t_done = 0;
     std::vector<int64_t> sum, count;
     std::vector<double> C;
     std::vector<int32_t> thr;
@@ -443,8 +443,10 @@ bool admit(kohler_server *s, std::unique_lock<std::mutex> &lk) {
         lk.lock();
 
         const int n = (int)items.size();
+        const int64_t t_issued = now_ns();
         for (const Item &it : items) {
             Request &r = s->reqs.at(it.ticket);
+            r.t_issued = t_issued;
             r.batch = n;
             r.graph = L.graph ? 1 : 0;
             L.tickets.push_back(it.ticket);
@@ -719,6 +721,7 @@ int kohler_server_wait(kohler_server *s, uint64_t ticket, int64_t *sum, int64_t 
         info->pad = 0;
         info->t_submit_ns = r.t_submit;
         info->t_launch_ns = r.t_launch;
+        info->t_issued_ns = r.t_issued;
         info->t_done_ns = r.t_done;
     }
     const int status = r.status;
