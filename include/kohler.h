@@ -126,7 +126,8 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
 
 /*
  * Launch plan control (the autotuner's knobs). A plan fixes, for one (dtype, M, nbhd) family:
- *   form        0 = automatic, 1 = banded joint histogram (M <= 256), 2 = marginal histograms
+ *   form        0 = automatic, 1 = banded joint histogram (M <= 256), 2 = marginal histograms,
+ *               3 = triangular joint histogram of (lo, hi) (M <= 256)
  *   band        number of gap rows of the banded table (1..64; form 1 only)
  *   block       threads per workgroup (256 or 512)
  *   grid        workgroups per launch (0 = automatic: enough to fill every compute unit)

@@ -23,7 +23,7 @@ from ._lib import (E_ARG, E_BUSY, E_CANCELED, E_CAPACITY, E_DEVICE, E_NOMEM, E_R
 __all__ = ["Context", "CurveResult", "KohlerError", "Plan", "Server", "curve", "default_context",
            "strerror"]
 
-FORM_AUTO, FORM_BAND, FORM_MARG = 0, 1, 2
+FORM_AUTO, FORM_BAND, FORM_MARG, FORM_TRI = 0, 1, 2, 3
 
 
 class KohlerError(RuntimeError):

@@ -40,8 +40,9 @@ bool valid_shape(int dtype, int64_t H, int64_t W, int64_t pitch, int32_t M, int3
 }
 
 bool valid_plan(const kohler_plan &pl, int dtype, int32_t M) {
-    if (pl.form != FORM_BAND && pl.form != FORM_MARG) return false;
+    if (pl.form != FORM_BAND && pl.form != FORM_MARG && pl.form != FORM_TRI) return false;
     if (pl.form == FORM_BAND && (M > kMaxMBand || pl.band < 1 || pl.band > kMaxBandRows)) return false;
+    if (pl.form == FORM_TRI && M > kMaxMBand) return false;
     if (pl.form == FORM_MARG && M > kMaxMMarg) return false;
     if (pl.block != 256 && pl.block != 512) return false;
     if (pl.grid < 0 || pl.grid > 65535) return false;
@@ -71,7 +72,7 @@ kohler_plan resolve_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, in
         auto it = ctx->plans.find(std::make_tuple(dtype, (int)M, (int)nbhd));
         pl = (it != ctx->plans.end()) ? it->second : default_plan(dtype, M);
     }
-    if (pl.form == FORM_BAND && M > kMaxMBand) pl = default_plan(dtype, M);
+    if ((pl.form == FORM_BAND || pl.form == FORM_TRI) && M > kMaxMBand) pl = default_plan(dtype, M);
     if (pl.replicas == 0) pl.replicas = -1;  // filled in below, once the grid is known
     if (pl.grid == 0) {
         const int per_cu = blocks_per_cu(dtype, nbhd, pl.form, pl.px_per_lane, M, pl.band, pl.block);
@@ -228,7 +229,7 @@ int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const k
         pl.form = d.form;
         if (pl.band == 0) pl.band = d.band;
     }
-    if (pl.form == FORM_MARG && pl.band == 0) pl.band = 1;
+    if ((pl.form == FORM_MARG || pl.form == FORM_TRI) && pl.band == 0) pl.band = 1;
     if (!valid_plan(pl, dtype, M)) return KOHLER_E_ARG;
     if (lds_bytes(pl.form, M, pl.band, pl.block) > kMaxLdsBytes) return KOHLER_E_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -519,6 +520,7 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
     if (M <= kMaxMBand)
         for (int b : {8, 16, 24, 32, 48, 64})
             if (b <= std::max(1, M - 1)) shapes.emplace_back(FORM_BAND, b);
+    if (M <= kMaxMBand) shapes.emplace_back(FORM_TRI, 1);
     if (M <= kMaxMMarg) shapes.emplace_back(FORM_MARG, 1);
     std::vector<int> ppls = dtype == KOHLER_U8 ? std::vector<int>{4, 8} : std::vector<int>{4};
     const std::vector<int> blocks = {256, 512};

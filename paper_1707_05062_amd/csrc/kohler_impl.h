@@ -55,7 +55,7 @@ struct KParams {
     int32_t *status;
 };
 
-enum Form { FORM_BAND = 1, FORM_MARG = 2 };
+enum Form { FORM_BAND = 1, FORM_MARG = 2, FORM_TRI = 3 };
 
 // Accumulator replicas: spreading the workgroups' global atomics over several copies keeps the
 // number of workgroups that contend for one word small.
@@ -88,7 +88,11 @@ constexpr int kRowStride = 257;
 // is larger; 16-byte aligned. Finalize for M <= 256 keeps two int64 partial sums per wave and level
 // (256 levels); for larger M, two int64 arrays of block + 1 entries and one byte per grey level.
 __host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int block) {
-    const size_t words = (form == FORM_BAND) ? ((size_t)band + 2) * kRowStride + 768 : 4 * (size_t)M;
+    // triangular form: M (M + 1) / 2 counters, 64 invalid-pair words, then hmin, hmax (M each) and
+    // hsum (2M, one spare)
+    const size_t words = (form == FORM_BAND)  ? ((size_t)band + 2) * kRowStride + 768
+                         : (form == FORM_TRI) ? (size_t)M * (M + 1) / 2 + 64 + 4 * (size_t)M
+                                              : 4 * (size_t)M;
     const size_t table = (words * 4 + 15) & ~(size_t)15;
     const size_t fin = M <= 256 ? (size_t)(block / 64) * 2 * 256 * 8
                                 : (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;

@@ -32,13 +32,15 @@
 // wave range). Horizontal neighbours across lanes come from DPP wave shifts; only lanes 0 and 63
 // load one extra pixel per row.
 
+#include <type_traits>
+
 #include "kohler_impl.h"
 
 namespace kohler {
 namespace {
 
-constexpr int kRowBatch = 8;  // rows whose loads a wave issues together before using them
-constexpr int kChunk = 8;     // units (rows of a strip) a wave claims at a time
+constexpr int kRowBatch = 4;  // rows whose loads a wave issues together before using them
+constexpr int kChunk = 4;     // units (rows of a strip) a wave claims at a time
 
 // Explicit address spaces keep loads, stores and atomics on the global (not flat) and LDS paths.
 #define KOHLER_GLOBAL __attribute__((address_space(1)))
@@ -207,18 +209,21 @@ struct RowSlot {
 template <typename Pix, int NB, int K, bool FULL, bool PACKED>
 __device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<Pix, K, PACKED> &sl) {
     constexpr int NW = Packed<Pix, K>::NW;
+    // column offsets are unsigned 32-bit, so each load is a wave-uniform row address (scalar
+    // registers) plus a zero-extended per-lane offset
+    const KOHLER_GLOBAL Pix *rp = gptr(row);
     if constexpr (PACKED) {
         // the last strip of a row is packed only when W is a multiple of K: lanes past the row
         // end re-read the row's last aligned chunk, and their pairs are masked out
-        const int cv = FULL ? c : min(c, W - K);
+        const uint32_t cv = (uint32_t)(FULL ? c : min(c, W - K));
         if constexpr (NW == 1) {
-            sl.v[0] = *gptr(reinterpret_cast<const uint32_t *>(row + cv));
+            sl.v[0] = *reinterpret_cast<const KOHLER_GLOBAL uint32_t *>(rp + cv);
         } else if constexpr (NW == 2) {
-            const u32x2 t = *gptr(reinterpret_cast<const u32x2 *>(row + cv));
+            const u32x2 t = *reinterpret_cast<const KOHLER_GLOBAL u32x2 *>(rp + cv);
             sl.v[0] = t.x;
             sl.v[1] = t.y;
         } else {
-            const u32x4 t = *gptr(reinterpret_cast<const u32x4 *>(row + cv));
+            const u32x4 t = *reinterpret_cast<const KOHLER_GLOBAL u32x4 *>(rp + cv);
             sl.v[0] = t.x;
             sl.v[1] = t.y;
             sl.v[2] = t.z;
@@ -226,11 +231,11 @@ __device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) sl.v[k] = (uint32_t)gptr(row)[FULL ? c + k : min(c + k, W - 1)];
+        for (int k = 0; k < K; ++k) sl.v[k] = (uint32_t)rp[(uint32_t)(FULL ? c + k : min(c + k, W - 1))];
     }
     // edge pixels: only lanes 63 (right) and 0 (left) use them, but every lane loads a valid column
-    sl.er = (uint32_t)gptr(row)[FULL ? c + K : min(c + K, W - 1)];
-    if constexpr (NB == 8) sl.el = (uint32_t)gptr(row)[max(c - 1, 0)];
+    sl.er = (uint32_t)rp[(uint32_t)(FULL ? c + K : min(c + K, W - 1))];
+    if constexpr (NB == 8) sl.el = (uint32_t)rp[(uint32_t)max(c - 1, 0)];
     else sl.el = 0;
 }
 
@@ -285,7 +290,52 @@ struct BandAcc {
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
     static constexpr bool kPixels = false;
     static constexpr bool kSpill = true;
+    typedef uint32_t P;
+    __device__ static __forceinline__ P prep(uint32_t v) { return v; }
 };
+
+// Triangular joint histogram of (hi, lo) with lo <= hi, for M <= 256: one LDS atomic per pair and no
+// large-gap path. Row hi starts at word T(hi) = hi (hi + 1) / 2, so the counter of a pair sits at
+// byte 4 T(hi) + 4 lo = 2 (hi^2 + hi) + 4 lo. Each pixel value u is prepared once as a = 4u and
+// x = u^2 + u; as x grows with u, a pair costs min(a), max(x) and one shift-add. Gap-0 pairs land
+// on the diagonal, which the projection skips; pairs outside the image land on a word of their
+// lane just past the table.
+struct TriPx {
+    uint32_t a, x;
+};
+struct TriAcc {
+    uint32_t dummy_x;  // 2 * dummy_x is the byte address of the invalid-pair words
+    uint32_t dmax, nb; // unused by this form
+    static constexpr uint32_t kScale = 1;
+    static constexpr bool kPixels = false;
+    static constexpr bool kSpill = false;
+    typedef TriPx P;
+    __device__ static __forceinline__ P prep(uint32_t u) { return TriPx{u << 2, __umul24(u, u) + u}; }
+    __device__ __forceinline__ void pair(P p, P q, bool valid) {
+        if (!valid) {
+            p.a = q.a = 4u * (threadIdx.x & 63u);
+            p.x = q.x = dummy_x;
+        }
+        const uint32_t lo4 = min(p.a, q.a);
+        const uint32_t hx = max(p.x, q.x);
+        lds_inc(lds_at((hx << 1) + lo4));
+    }
+    __device__ __forceinline__ bool needs_spill() const { return false; }
+    __device__ __forceinline__ void pixel(P, uint32_t, bool) {}
+};
+
+// Words of the triangular table for M levels (without the invalid-pair words).
+__host__ __device__ constexpr uint32_t tri_words(uint32_t M) { return M * (M + 1u) / 2u; }
+
+// Lane shifts of a prepared pixel (see from_next_lane / from_prev_lane).
+__device__ __forceinline__ uint32_t next_px(uint32_t v, uint32_t edge) { return from_next_lane(v, edge); }
+__device__ __forceinline__ uint32_t prev_px(uint32_t v, uint32_t edge) { return from_prev_lane(v, edge); }
+__device__ __forceinline__ TriPx next_px(TriPx v, TriPx edge) {
+    return TriPx{from_next_lane(v.a, edge.a), from_next_lane(v.x, edge.x)};
+}
+__device__ __forceinline__ TriPx prev_px(TriPx v, TriPx edge) {
+    return TriPx{from_prev_lane(v.a, edge.a), from_prev_lane(v.x, edge.x)};
+}
 
 // hmax and hsum of the pairs with gap > nb (second pass over a row, rare); values scaled by 4, so
 // 4*hi and 4*(lo + hi) are already byte offsets.
@@ -301,6 +351,7 @@ struct SpillAcc {
     }
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
     static constexpr bool kPixels = false;
+    typedef uint32_t P;
 };
 
 // Marginal histograms: low value and value sum per pair, degree-weighted value per pixel.
@@ -320,6 +371,8 @@ struct MargAcc {
     static constexpr uint32_t kScale = 1;
     uint32_t dmax, nb;
     __device__ __forceinline__ bool needs_spill() const { return false; }
+    typedef uint32_t P;
+    __device__ static __forceinline__ P prep(uint32_t v) { return v; }
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -327,12 +380,11 @@ struct MargAcc {
 
 // FULL: every column of the strip and the column right of it lie inside the image, so no
 // per-column test is needed (all strips but the last one of a row).
-template <int NB, int K, bool FULL, class Acc>
-__device__ __forceinline__ void row_pairs(const uint32_t (&cur)[K], const uint32_t (&nxt)[K],
-                                          uint32_t er_cur, uint32_t er_nxt, uint32_t el_nxt,
+template <int NB, int K, bool FULL, class Acc, class P>
+__device__ __forceinline__ void row_pairs(const P (&cur)[K], const P (&nxt)[K], P er_cur, P er_nxt, P el_nxt,
                                           bool has_up, bool has_down, int c, int W, Acc &acc) {
     // right neighbour of this lane's last pixel: next lane's first pixel, or the edge load (lane 63)
-    const uint32_t rn = from_next_lane(cur[0], er_cur);
+    const P rn = next_px(cur[0], er_cur);
 #pragma unroll
     for (int k = 0; k + 1 < K; ++k) acc.pair(cur[k], cur[k + 1], FULL || c + k + 1 < W);
     acc.pair(cur[K - 1], rn, FULL || c + K < W);
@@ -340,8 +392,8 @@ __device__ __forceinline__ void row_pairs(const uint32_t (&cur)[K], const uint32
 #pragma unroll
         for (int k = 0; k < K; ++k) acc.pair(cur[k], nxt[k], FULL || c + k < W);
         if constexpr (NB == 8) {
-            const uint32_t rnd = from_next_lane(nxt[0], er_nxt);
-            const uint32_t lnd = from_prev_lane(nxt[K - 1], el_nxt);
+            const P rnd = next_px(nxt[0], er_nxt);
+            const P lnd = prev_px(nxt[K - 1], el_nxt);
 #pragma unroll
             for (int k = 0; k + 1 < K; ++k) acc.pair(cur[k], nxt[k + 1], FULL || c + k + 1 < W);
             acc.pair(cur[K - 1], rnd, FULL || c + K < W);
@@ -409,7 +461,18 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
                     e1 = min(e1, Mm1);
                     l1 = min(l1, Mm1);
                 }
-                row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, acc);
+                if constexpr (std::is_same<typename Acc::P, uint32_t>::value) {
+                    row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, acc);
+                } else {
+                    typename Acc::P pc[K], pn[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        pc[k] = Acc::prep(cur[k]);
+                        pn[k] = Acc::prep(nxt[k]);
+                    }
+                    row_pairs<NB, K, FULL>(pc, pn, Acc::prep(e0), Acc::prep(e1), Acc::prep(l1), row > 0, has_down,
+                                           c, W, acc);
+                }
                 if constexpr (Acc::kSpill) {
                     if (__any(acc.needs_spill())) row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, spill);
                     acc.dmax = 0;
@@ -419,26 +482,33 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
     }
 }
 
+// Rows [r0, r1) of strip s of one image, by one wave.
+template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
+__device__ __forceinline__ void strip_range(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
+                                            Acc &acc, Spill &spill, uint32_t &vmax) {
+    constexpr int SW = 64 * K;
+    if ((int64_t)(s + 1) * SW < im.W) {
+        if (im.vec_ok)
+            strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
+        else
+            strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
+    } else if (im.vec_ok && im.W % K == 0) {
+        strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
+    } else {
+        strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
+    }
+}
+
 // Units [la, lb) of one image (image-local, strip-major), by one wave.
 template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
 __device__ __forceinline__ void wave_units(const KImage &im, int64_t la, int64_t lb, uint32_t Mm1, Acc &acc,
                                            Spill &spill, uint32_t &vmax) {
-    constexpr int SW = 64 * K;
     int64_t u = la;
     while (u < lb) {
         const int s = (int)(u / im.H);
         const int64_t r = u - (int64_t)s * im.H;
         const int64_t rend = min(im.H, r + (lb - u));
-        if ((int64_t)(s + 1) * SW < im.W) {
-            if (im.vec_ok)
-                strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r, rend, Mm1, acc, spill, vmax);
-            else
-                strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r, rend, Mm1, acc, spill, vmax);
-        } else if (im.vec_ok && im.W % K == 0) {
-            strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r, rend, Mm1, acc, spill, vmax);
-        } else {
-            strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r, rend, Mm1, acc, spill, vmax);
-        }
+        strip_range<Pix, NB, K, CLAMP>(im, s, r, rend, Mm1, acc, spill, vmax);
         u += rend - r;
     }
 }
@@ -471,6 +541,24 @@ __device__ __forceinline__ int64_t second_diff(int64_t lohi, const lds_u32 *hsum
     return e;
 }
 
+// Sums of LDS words whose addresses follow from an index i in [i0, i1] (inclusive): `addr(i)` gives
+// the word. Loads are issued 16 at a time before any is added (the index is clamped to the range,
+// so every address is valid, and the surplus is dropped), so a sum of n words costs about n / 16 LDS
+// round trips instead of n / 4.
+constexpr int kLdsBatch = 16;
+template <class Addr>
+__device__ __forceinline__ uint32_t lds_sum(const lds_u32 *tab, int i0, int i1, Addr addr) {
+    uint32_t acc = 0;
+    for (int i = i0; i <= i1; i += kLdsBatch) {
+        uint32_t t[kLdsBatch];
+#pragma unroll
+        for (int j = 0; j < kLdsBatch; ++j) t[j] = tab[addr(min(i + j, i1))];
+#pragma unroll
+        for (int j = 0; j < kLdsBatch; ++j) acc += (i + j <= i1) ? t[j] : 0u;
+    }
+    return acc;
+}
+
 __device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, int64_t *acc) {
     const int M = p.M;
     const uint32_t nb = (uint32_t)p.band;
@@ -478,42 +566,20 @@ __device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, i
     lds_u32 *tab = lds, *lospill = lds + (nb + 1u) * RS, *smax = lds + (nb + 2u) * RS, *ssum = smax + 256;
     // project rows 1..nb of the (gap, lo) table on rows (hmin), diagonals (hmax) and anti-diagonals
     // (hsum), adding the large-gap pairs' own counts; results overwrite lospill, smax and ssum.
-    // Four independent partial sums keep several LDS reads in flight per thread.
+    const int inb = (int)nb;
     for (int x = threadIdx.x; x < 4 * M - 1; x += blockDim.x) {
-        uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0;
         if (x < M) {
-            const int v = x;
-            uint32_t d = 1;
-            for (; d + 3 <= nb; d += 4) {
-                q0 += tab[d * RS + v];
-                q1 += tab[(d + 1) * RS + v];
-                q2 += tab[(d + 2) * RS + v];
-                q3 += tab[(d + 3) * RS + v];
-            }
-            for (; d <= nb; ++d) q0 += tab[d * RS + v];
-            lospill[v] += q0 + q1 + q2 + q3;
+            const int v = x;  // (d, v) for d = 1 .. nb
+            lospill[v] += lds_sum(tab, 1, inb, [&](int d) { return d * (int)RS + v; });
         } else if (x < 2 * M) {
-            const int v = x - M;
-            const uint32_t dm = min(nb, (uint32_t)v);
-            uint32_t d = 1;
-            for (; d + 3 <= dm; d += 4) {
-                q0 += tab[d * RS + v - d];
-                q1 += tab[(d + 1) * RS + v - d - 1];
-                q2 += tab[(d + 2) * RS + v - d - 2];
-                q3 += tab[(d + 3) * RS + v - d - 3];
-            }
-            for (; d <= dm; ++d) q0 += tab[d * RS + v - d];
-            smax[v] += q0 + q1 + q2 + q3;
+            const int v = x - M;  // (d, v - d) for d = 1 .. min(nb, v)
+            smax[v] += lds_sum(tab, 1, min(inb, v), [&](int d) { return d * ((int)RS - 1) + v; });
         } else {
-            const int s = x - 2 * M;
-            const uint32_t dm = min(nb, (uint32_t)s);
-            uint32_t d = 2 - (s & 1);
-            for (; d + 2 <= dm; d += 4) {
-                q0 += tab[d * RS + (s - d) / 2];
-                q1 += tab[(d + 2) * RS + (s - d - 2) / 2];
-            }
-            for (; d <= dm; d += 2) q0 += tab[d * RS + (s - d) / 2];
-            ssum[s] += q0 + q1;
+            const int s = x - 2 * M;  // (d, (s - d) / 2) for d = d0, d0 + 2, .. <= min(nb, s)
+            const int d0 = 2 - (s & 1);
+            const int n = min(inb, s) >= d0 ? (min(inb, s) - d0) / 2 : -1;  // last index
+            const int base = d0 * (int)RS + (s - d0) / 2;
+            ssum[s] += lds_sum(tab, 0, n, [&](int k) { return base + k * (2 * (int)RS - 1); });
         }
     }
     __syncthreads();
@@ -521,6 +587,42 @@ __device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, i
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
         const int64_t d1 = (int64_t)lospill[v] - (int64_t)smax[v];
         const int64_t e = v >= 1 ? second_diff((int64_t)lospill[v - 1] + smax[v - 1], ssum, v, M) : 0;
+        sink ^= add_levels(acc, M, p.packed_acc != 0, v, d1, e);
+    }
+    return sink;
+}
+
+// Project the triangular table onto hmax (row sums without the diagonal), hmin (column sums below
+// the diagonal) and hsum (anti-diagonal sums without the diagonal). Thread task v < M: row v and
+// column v (M - 1 reads); thread task M + s: anti-diagonals s and 2M - 2 - s (about s reads).
+__device__ __forceinline__ uint64_t merge_tri(const KParams &p, lds_u32 *lds, int64_t *acc) {
+    const int M = p.M;
+    const lds_u32 *tab = lds;
+    lds_u32 *hmin = lds + tri_words((uint32_t)M) + 64, *hmax = hmin + M, *hsum = hmax + M;
+    // anti-diagonal s: (hi, lo) = (s - lo, lo) for lo from max(0, s - M + 1) to (s - 1) / 2
+    auto anti = [&](int s) -> uint32_t {
+        if (s < 1) return 0u;
+        const int lo0 = max(0, s - M + 1), lo1 = (s - 1) / 2;
+        return lds_sum(tab, lo0, lo1, [&](int lo) { return (int)tri_words((uint32_t)(s - lo)) + lo; });
+    };
+    for (int x = threadIdx.x; x < 2 * M; x += blockDim.x) {
+        if (x < M) {
+            const int v = x;
+            const int rb = (int)tri_words((uint32_t)v);  // row v: lo = 0 .. v - 1
+            hmax[v] = lds_sum(tab, 0, v - 1, [&](int lo) { return rb + lo; });
+            // column v: rows h = v + 1 .. M - 1
+            hmin[v] = lds_sum(tab, v + 1, M - 1, [&](int h) { return (int)tri_words((uint32_t)h) + v; });
+        } else {
+            const int s = x - M, s2 = 2 * M - 2 - s;
+            hsum[s] = anti(s);
+            if (s2 != s) hsum[s2] = anti(s2);
+        }
+    }
+    __syncthreads();
+    uint64_t sink = 0;
+    for (int v = threadIdx.x; v < M; v += blockDim.x) {
+        const int64_t d1 = (int64_t)hmin[v] - (int64_t)hmax[v];
+        const int64_t e = v >= 1 ? second_diff((int64_t)hmin[v - 1] + hmax[v - 1], hsum, v, M) : 0;
         sink ^= add_levels(acc, M, p.packed_acc != 0, v, d1, e);
     }
     return sink;
@@ -619,8 +721,8 @@ __device__ __forceinline__ void finalize_wave(const KParams &p, int i, lds_u32 *
     KOHLER_LDS int64_t *part = reinterpret_cast<KOHLER_LDS int64_t *>(lds);  // [nw][2][256]
     const int tb = kWaveT * lane;
 
-    // 1. replica sums, a share per wave; every load is issued before any is used (replica indices
-    //    past R and levels past M re-read a valid word and are dropped), then the words are cleared
+    // 1. replica sums, a share per wave; a wave issues all its loads before it uses any (levels past
+    //    M re-read a valid word and are dropped), then clears the words it read
     {
         constexpr int kRepsPerWave = kMaxReplicas / 4;  // blockDim.x >= 256
         // sum of this wave's replicas of the array starting at word `base` of each replica
@@ -628,9 +730,15 @@ __device__ __forceinline__ void finalize_wave(const KParams &p, int i, lds_u32 *
             uint64_t v[kRepsPerWave][kWaveT];
 #pragma unroll
             for (int k = 0; k < kRepsPerWave; ++k) {
-                const int r = min(w + k * nw, R - 1);
+                const int r = w + k * nw;
+                if (r < R) {  // wave-uniform: a wave loads only the replicas it sums
 #pragma unroll
-                for (int q = 0; q < kWaveT; ++q) v[k][q] = load_shared(acc + r * RS + base + (tb + q < M ? tb + q : 0));
+                    for (int q = 0; q < kWaveT; ++q)
+                        v[k][q] = load_shared(acc + r * RS + base + (tb + q < M ? tb + q : 0));
+                } else {
+#pragma unroll
+                    for (int q = 0; q < kWaveT; ++q) v[k][q] = 0;
+                }
             }
 #pragma unroll
             for (int q = 0; q < kWaveT; ++q) s[q] = 0;
@@ -674,9 +782,12 @@ __device__ __forceinline__ void finalize_wave(const KParams &p, int i, lds_u32 *
 #pragma unroll
     for (int q = 0; q < kWaveT; ++q) {
         int64_t a = 0, b = 0;
-        for (int v = 0; v < nw; ++v) {
-            a += part[(2 * v) * kWaveMaxM + tb + q];
-            b += part[(2 * v + 1) * kWaveMaxM + tb + q];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {  // blockDim.x <= 512: at most 8 waves
+            const int64_t pa = part[(2 * min(v, nw - 1)) * kWaveMaxM + tb + q];
+            const int64_t pb = part[(2 * min(v, nw - 1) + 1) * kWaveMaxM + tb + q];
+            a += v < nw ? pa : 0;
+            b += v < nw ? pb : 0;
         }
         if (packed) {
             // E * 2^32 + D1 summed as one word: |D1| < 2^31 because the image has < 2^30 pairs
@@ -1071,6 +1182,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
 
     uint32_t table_words;
     if constexpr (FORM == FORM_BAND) table_words = (((uint32_t)p.band + 2u) * kRowStride + 768u + 3u) & ~3u;
+    else if constexpr (FORM == FORM_TRI) table_words = (tri_words((uint32_t)p.M) + 64u + 3u) & ~3u;
     else table_words = 4u * (uint32_t)p.M;
 
     auto clear_tables = [&]() {
@@ -1090,6 +1202,10 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
             SpillAcc spill{4u * (nb + 2u) * kRowStride, 4u * ((nb + 2u) * kRowStride + 256u), nb};
             chunks(acc, spill, vmax, Mm1 * BandAcc::kScale);
             vmax /= BandAcc::kScale;
+        } else if constexpr (FORM == FORM_TRI) {
+            TriAcc acc{2u * tri_words((uint32_t)p.M), 0u, 0u};
+            SpillAcc spill{0u, 0u, 0u};  // not used by the triangular form
+            chunks(acc, spill, vmax, Mm1);
         } else {
             MargAcc acc{lds, lds + p.M, lds + 2 * p.M, 0u, 0u};
             SpillAcc spill{0u, 0u, 0u};  // not used by the marginal form
@@ -1112,6 +1228,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         if (units == 0) return;  // uniform: nothing to add, and no ticket to take
         int64_t *acc_g = p.acc + (int64_t)i * p.acc_stride + (int64_t)(blockIdx.x % (uint32_t)p.nrep) * p.rep_stride;
         if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
+        else if constexpr (FORM == FORM_TRI) sink ^= merge_tri(p, lds, acc_g);
         else sink ^= merge_marg(p, lds, acc_g);
 
         // every contribution of this workgroup has been performed once its returned value is here:
@@ -1125,8 +1242,12 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         }
         __syncthreads();
         if (bs.last) {
-            if (p.M <= kWaveMaxM) finalize_wave(p, i, lds);
-            else finalize(p, i, lds, bs);
+            if constexpr (FORM == FORM_MARG) {
+                if (p.M <= kWaveMaxM) finalize_wave(p, i, lds);
+                else finalize(p, i, lds, bs);
+            } else {
+                finalize_wave(p, i, lds);
+            }
         }
         __syncthreads();
     };
@@ -1154,12 +1275,14 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
             return (uint32_t)__builtin_amdgcn_readfirstlane(k);
         };
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
+            // chunk numbers stay below 2^32 (at most 2^40 pixels, chunks of kChunk rows by at least 256
+            // columns),
+            // so the decode is a 32-bit division by a wave-uniform value
             for (uint32_t j = claim(); j < mine; j = claim()) {
-                const int64_t c = (int64_t)g + (int64_t)j * G;
-                const int64_t blk = c / ns, strip = c - blk * ns;
-                const int64_t ca = strip * im.H + blk * kChunk;  // strip-major unit numbers
-                const int64_t cb = strip * im.H + min(im.H, (blk + 1) * kChunk);
-                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
+                const uint32_t c = (uint32_t)g + j * (uint32_t)G;
+                const uint32_t blk = c / (uint32_t)ns, strip = c - blk * (uint32_t)ns;
+                const int64_t r0 = (int64_t)blk * kChunk;
+                strip_range<Pix, NB, K, CLAMP>(im, (int)strip, r0, min(im.H, r0 + kChunk), mm1, acc, spill, vm);
             }
         });
         // units of this workgroup: kChunk rows per chunk, less the short chunks of the last row block
@@ -1204,6 +1327,9 @@ const void *pick_form(int form, bool clamp) {
     if (form == FORM_BAND)
         return clamp ? reinterpret_cast<const void *>(curve_kernel<Pix, NB, K, FORM_BAND, true>)
                      : reinterpret_cast<const void *>(curve_kernel<Pix, NB, K, FORM_BAND, false>);
+    if (form == FORM_TRI)
+        return clamp ? reinterpret_cast<const void *>(curve_kernel<Pix, NB, K, FORM_TRI, true>)
+                     : reinterpret_cast<const void *>(curve_kernel<Pix, NB, K, FORM_TRI, false>);
     return clamp ? reinterpret_cast<const void *>(curve_kernel<Pix, NB, K, FORM_MARG, true>)
                  : reinterpret_cast<const void *>(curve_kernel<Pix, NB, K, FORM_MARG, false>);
 }

@@ -124,7 +124,7 @@ def test_plan_sweep(ctx, K):
         ref = reference(img, 256, nbhd)
         plans = []
         for form, band in [(K.FORM_BAND, 1), (K.FORM_BAND, 2), (K.FORM_BAND, 7), (K.FORM_BAND, 32),
-                           (K.FORM_BAND, 64), (K.FORM_MARG, 0)]:
+                           (K.FORM_BAND, 64), (K.FORM_MARG, 0), (K.FORM_TRI, 0)]:
             for block in (256, 512):
                 for grid in (1, 3, 17, 0):
                     for ppl in (4, 8):
@@ -282,3 +282,68 @@ def test_bad_arguments(ctx, K):
         assert e.value.status == K.E_ARG
     with pytest.raises(K.KohlerError):
         ctx.curve(img, 256, 4, capacity=-1)
+
+
+# ----------------------------------------------------------------------------------------------
+# the triangular joint histogram (one counter per (lo, hi), no large-gap path) on the same cases
+
+def test_tri_form_cases(K):
+    c = K.Context(0)
+    try:
+        rng = np.random.default_rng(33)
+        for dtype in (1, 2):
+            for M in (1, 2, 3, 5, 8, 16, 33, 200, 256):
+                for nbhd in (4, 8):
+                    c.set_plan(dtype, M, nbhd, form=K.FORM_TRI)
+        n = 0
+        for H in range(1, 7):
+            for W in range(1, 7):
+                for M in (1, 2, 3, 5, 8, 16, 33, 256):
+                    for nbhd in (4, 8):
+                        img = rng.integers(0, M, size=(H, W)).astype(np.uint8)
+                        assert_result(c.curve(img, M, nbhd), reference(img, M, nbhd), what=f"tri {H}x{W} M={M} N{nbhd}")
+                        n += 1
+        say("tri tiny cases", n)
+        for kind in ("uniform", "levels", "smooth"):
+            for (h, w) in [(1, 2000), (257, 1), (77, 515), (130, 1031)]:
+                for M, dt in [(256, np.uint8), (200, np.uint8), (256, np.uint16), (33, np.uint16)]:
+                    img = gen.random_image(rng, h, w, M, dt, kind)
+                    for nbhd in (4, 8):
+                        res = c.curve(to_device(img), M, nbhd)
+                        assert_result(res, reference(img, M, nbhd), what=f"tri {kind} {h}x{w} M={M} {dt.__name__} N{nbhd}")
+        img = gen.cfg1_image()
+        for nbhd in (4, 8):
+            assert_result(c.curve(to_device(img), 256, nbhd), reference(img, 256, nbhd), what=f"tri cfg1 N{nbhd}")
+        # range error under the triangular form, then recovery
+        bad = gen.random_image(rng, 50, 90, 200, np.uint8, "smooth")
+        bad[10, 10] = 230
+        res = c.curve(to_device(bad), 200, 4, check=False)
+        assert res.status == K.E_RANGE
+        bad[10, 10] = 0
+        assert_result(c.curve(to_device(bad), 200, 4), reference(bad, 200, 4), what="tri after range error")
+        # batched launch under the triangular form
+        imgs = [gen.random_image(rng, h, w, 256, np.uint8, ["uniform", "levels", "smooth"][i % 3])
+                for i, (h, w) in enumerate([(1, 1), (3, 700), (129, 257), (600, 41), (255, 1030), (64, 64)])]
+        out = c.curve_batch([to_device(x) for x in imgs], 256, 4)
+        import torch
+        torch.cuda.synchronize()
+        ints = out["ints"].cpu().numpy()
+        nb = len(imgs)
+        for i, x in enumerate(imgs):
+            r = reference(x, 256, 4)
+            nt = int(ints[i])
+            assert_same(out["sum"][i].cpu().numpy(), out["count"][i].cpu().numpy(), out["C"][i].cpu().numpy(),
+                        out["thr"][i].cpu().numpy()[:nt], int(ints[nb + i]), nt, r, what=f"tri batch {i}")
+    finally:
+        c.close()
+
+
+def test_tri_form_cfg2_full_size(K):
+    img = gen.cfg2_image()
+    c = K.Context(0)
+    try:
+        c.set_plan(1, 256, 4, form=K.FORM_TRI)
+        res = c.curve(to_device(img), 256, 4)
+        assert_result(res, reference(img, 256, 4), what="tri cfg2")
+    finally:
+        c.close()
