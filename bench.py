@@ -12,9 +12,9 @@ Also measured in the same run (reported beside the headline, not as separate lin
   batched  96 uint8 images of log-uniform sizes (128^2 .. 4000x3000) in one persistent launch vs the
            plain kernel launched once per image on one stream;
   served   a Poisson stream of 240 requests/s (70% 1080p video frames, 20% 4K frames, 10% 18 MP
-           stills) through the serving loop vs the same loop restricted to one image per launch,
-           with p50/p99 latency from scheduled arrival to results in host memory, plus a burst that
-           saturates both.
+           stills) through the serving loop (with and without the per-frame HIP graph) vs the same
+           loop restricted to one image per launch, with p50/p99 latency from scheduled arrival to
+           results in host memory, plus a burst that saturates them.
 
 Prints ONE JSON line with the headline throughput in Gpixel/s, the roofline of the curve kernel
 (algorithmic bytes / average kernel duration from HIP events on the launch stream) and the CPU
@@ -367,6 +367,7 @@ def served(args, K, ctx, torch, gen) -> dict:
     check_srv.close()
 
     server_kw = dict(slots=32, lanes=2, max_batch=16, use_graphs=True, hbm_budget_bytes=2 << 30)
+    eager_kw = dict(server_kw, use_graphs=False)
     plain_kw = dict(slots=1, lanes=1, max_batch=1, use_graphs=False, hbm_budget_bytes=256 << 20)
     trace = make_trace(args.rate, args.serve_seconds + 1.0)
     log(f"served: {len(trace)} arrivals over {args.serve_seconds + 1.0:.0f} s")
@@ -376,15 +377,18 @@ def served(args, K, ctx, torch, gen) -> dict:
                        "pinned host frames cycled from a pool; latency = scheduled arrival to "
                        "results in host memory",
            "results_match_context": ok,
-           "server_config": server_kw, "plain_config": plain_kw}
+           "server_config": server_kw, "server_eager_config": eager_kw, "plain_config": plain_kw}
     res["server"] = run_trace(K, ctx, pool, trace, 1.0, server_kw)
     log(f"served server: {res['server']['p50_ms']:.3f}/{res['server']['p99_ms']:.3f} ms p50/p99")
+    res["server_eager"] = run_trace(K, ctx, pool, trace, 1.0, eager_kw)
+    log(f"served server without graphs: {res['server_eager']['p50_ms']:.3f}/{res['server_eager']['p99_ms']:.3f} ms p50/p99")
     res["plain"] = run_trace(K, ctx, pool, trace, 1.0, plain_kw)
     log(f"served plain:  {res['plain']['p50_ms']:.3f}/{res['plain']['p99_ms']:.3f} ms p50/p99")
     rng = np.random.default_rng(55)
     burst = [(0.0, int(rng.choice(3, p=SERVE_MIX))) for _ in range(args.burst)]
     res["burst"] = {"requests": len(burst),
                     "server": run_trace(K, ctx, pool, burst, 0.0, server_kw, burst=True),
+                    "server_eager": run_trace(K, ctx, pool, burst, 0.0, eager_kw, burst=True),
                     "plain": run_trace(K, ctx, pool, burst, 0.0, plain_kw, burst=True)}
     log(f"burst: server {res['burst']['server']['gpixel_s']:.1f} Gpx/s, "
         f"plain {res['burst']['plain']['gpixel_s']:.1f} Gpx/s")

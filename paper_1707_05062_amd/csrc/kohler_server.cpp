@@ -139,6 +139,10 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t h2d = nullptr, kern = nullptr, d2h = nullptr;
+    // arguments the instantiated graph holds now; a node is updated only when its own change
+    const void *src = nullptr;
+    const void *img = nullptr;
+    int slot = -1;
 };
 
 constexpr size_t kMaxGraphs = 64;
@@ -282,18 +286,39 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
                 if (g.graph) (void)hipGraphDestroy(g.graph);
                 return pick_status(e);
             }
+            g.src = it.img;
+            g.img = p.img0.ptr;
+            g.slot = it.slot;
             found = s->graphs.emplace(key, g).first;
             L.built = true;
         } else {
+            // the image's host address changes with every frame; its arena block and the slot
+            // usually repeat (first fit, last-freed slot first), and then so do the kernel's
+            // arguments and the result copy
             GraphEntry &g = found->second;
-            if (!it.on_device)
+            if (!it.on_device && g.src != it.img) {
                 e = hipGraphExecMemcpyNodeSetParams1D(g.exec, g.h2d, img_dst, it.img, it.bytes,
                                                       hipMemcpyHostToDevice);
-            if (e == hipSuccess) e = hipGraphExecKernelNodeSetParams(g.exec, g.kern, &kn);
-            if (e == hipSuccess)
+                g.src = it.img;
+            }
+            if (e == hipSuccess && (g.img != p.img0.ptr || g.slot != it.slot)) {
+                e = hipGraphExecKernelNodeSetParams(g.exec, g.kern, &kn);
+                g.img = p.img0.ptr;
+                // the host-to-device copy's destination moved with the image
+                if (e == hipSuccess && !it.on_device)
+                    e = hipGraphExecMemcpyNodeSetParams1D(g.exec, g.h2d, img_dst, it.img, it.bytes,
+                                                          hipMemcpyHostToDevice);
+            }
+            if (e == hipSuccess && g.slot != it.slot) {
                 e = hipGraphExecMemcpyNodeSetParams1D(g.exec, g.d2h, rec_h, rec_d, s->rec_bytes,
                                                       hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return pick_status(e);
+                g.slot = it.slot;
+            }
+            if (e != hipSuccess) {
+                g.src = g.img = nullptr;  // unknown state: update every node next time
+                g.slot = -1;
+                return pick_status(e);
+            }
         }
         if ((e = hipGraphLaunch(found->second.exec, stream)) != hipSuccess) return pick_status(e);
         L.graph = true;
