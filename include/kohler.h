@@ -158,8 +158,10 @@ int kohler_get_plan(kohler_ctx *ctx, int dtype, int64_t H, int64_t W, int32_t M,
  * kohler_curve_batch (n device images; n == 1 tunes the single-image launch, n > 1 the batched
  * one). The search is a coordinate descent, two passes over the knobs in the order tile shape
  * (form and band), px_per_lane, block, grid (automatic or 1..4 workgroups per compute unit) and
- * replicas, starting from the default plan; each candidate gets two warm-up launches and `reps`
- * timed ones (0 means 5) on the context's stream, and its median time counts.
+ * replicas, starting from the default plan, then a joint sweep of band (banded form),
+ * px_per_lane, grid and replicas (1, 2, 4, 8) around the result; each
+ * candidate gets two warm-up launches and `reps` timed ones (0 means 5) on the context's stream,
+ * and its median time counts.
  *   best     out: the chosen plan (grid and replicas may be 0 = automatic)
  *   best_us  out (may be NULL): its median launch time in microseconds
  * It allocates and frees temporary device outputs and synchronises the context's stream, so it

@@ -578,6 +578,39 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
             try_plan(pl);
         }
     }
+    // strip width, band, grid and merge schedule interact (occupancy, replicas per workgroup
+    // count): a last joint sweep over them for the chosen form and block
+    if (st == KOHLER_OK) {
+        const kohler_plan base = cur;
+        std::vector<int> bands = {base.band};
+        if (base.form == FORM_BAND)
+            for (int b : {16, 32, 48, 64})
+                if (b != base.band && b <= std::max(1, M - 1)) bands.push_back(b);
+        for (int bv : bands)
+            for (int pv : ppls) {
+                const int per_cu = blocks_per_cu(dtype, nbhd, base.form, pv, M, bv, base.block);
+                for (int gv = 0; gv <= std::min(4, per_cu); ++gv)
+                    for (int rv : {1, 2, 4, 8}) {
+                        if (st != KOHLER_OK) break;
+                        kohler_plan pl = base;
+                        pl.band = bv;
+                        pl.px_per_lane = pv;
+                        pl.grid = gv * ctx->num_cus;
+                        pl.replicas = rv;
+                        double us = 0.0;
+                        const int r = time_plan(pl, &us);
+                        if (r == KOHLER_E_ARG) continue;
+                        if (r != KOHLER_OK) {
+                            st = r;
+                            break;
+                        }
+                        if (us < cur_us) {
+                            cur = pl;
+                            cur_us = us;
+                        }
+                    }
+            }
+    }
     for (auto &x : ev)
         if (x) (void)hipEventDestroy(x);
     (void)hipFree(buf);

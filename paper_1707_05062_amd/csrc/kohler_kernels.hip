@@ -435,9 +435,16 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
         RowSlot<Pix, K, PACKED> ring[kRowBatch + 1];
         // unconditional loads (rows past the range re-read rlast, a cache hit): with a fixed number
         // of loads in flight the compiler can wait for exactly the row it is about to use
+        {
+            // row addresses by scalar increments (the rows past rlast re-read rlast)
+            const Pix *rowp = base + rb * pitch;
+            const int64_t room = rlast - rb;
 #pragma unroll
-        for (int j = 0; j <= kRowBatch; ++j)
-            load_slot<Pix, NB, K, FULL, PACKED>(base + min(rb + j, rlast) * pitch, c, W, ring[j]);
+            for (int j = 0; j <= kRowBatch; ++j) {
+                load_slot<Pix, NB, K, FULL, PACKED>(rowp, c, W, ring[j]);
+                if (j < room) rowp += pitch;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < kRowBatch; ++j) {
             if (j < nr) {
