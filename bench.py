@@ -85,8 +85,9 @@ def kernel_sources_digest() -> str:
 
 
 def measured_traffic(plan: dict):
-    """HBM bytes per launch from the stored FETCH_SIZE/WRITE_SIZE measurement, if it was taken on
-    this kernel build with the same tile width and grid (else None)."""
+    """HBM bytes per launch from the stored FETCH_SIZE/WRITE_SIZE measurements, if one was taken on
+    this kernel build with the same strip width and grid (the other plan fields do not change the
+    memory traffic of a launch beyond a few KB); else None."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
@@ -94,9 +95,12 @@ def measured_traffic(plan: dict):
         return None
     if t.get("kernel_sources_sha256") != kernel_sources_digest():
         return None
-    if t.get("px_per_lane") != plan.get("px_per_lane") or t.get("grid") != plan.get("grid"):
-        return None
-    return {"bytes": t["traffic_bytes_per_launch"], "source": t["source"]}
+    for row in t.get("by_tile_and_grid", []):
+        if row["px_per_lane"] == plan.get("px_per_lane") and row["grid"] == plan.get("grid"):
+            return {"bytes": row["traffic_bytes_per_launch"],
+                    "source": f"{t['method']}; measured with plan {row['plan']}"}
+    return None
+
 
 def parse_plan(s: str) -> dict:
     keys = ("form", "band", "block", "grid", "px_per_lane", "replicas")
