@@ -297,6 +297,8 @@ def run_trace(K, ctx, pool, trace, warm_s, server_kw, burst=False):
         t0 = time.monotonic_ns() + 20_000_000
 
         def submitter():
+            while time.monotonic_ns() < t0:  # the clock starts at t0, for a burst too
+                time.sleep(0.0005)
             for (ta, ci) in trace:
                 c = SERVE_CLASSES[ci]
                 frame = pool[c][counters[c] % len(pool[c])]
