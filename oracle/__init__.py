@@ -6,7 +6,8 @@ product path (the HIP library and its Python binding) never does, and it shares 
 Reference: G. Noyel, arXiv 1707.05062. ``curve`` is the definition of Sec. 2.1 (eqs (1)-(3)) written
 out over every threshold and every ordered neighbour pair; ``alg1`` is Algorithm 1 of Sec. 3.1 over
 the half neighbourhood of Sec. 3.2; ``thresholds`` gives the curve's local maxima and the optimum of
-eq (4). The C sources are in ``kohler_oracle.c``; ``build()`` compiles them with gcc and OpenMP.
+eq (4); ``segment`` labels pixels by the classes those thresholds cut (Sec. 2.1). The C sources are
+in ``kohler_oracle.c``; ``build()`` compiles them with gcc and OpenMP.
 """
 from __future__ import annotations
 
@@ -128,3 +129,21 @@ def full(img: np.ndarray, M: int, nbhd: int = 4, lib=None):
     s, k, c = curve(img, M, nbhd, lib=lib)
     thr, t0, _, _ = thresholds(s, k, lib=lib)
     return s, k, c, thr, t0
+
+
+def segment(img: np.ndarray, thresholds_, rows_per_step: int = 256) -> np.ndarray:
+    """Class label of every pixel for ascending thresholds t_1 < ... < t_k (Sec. 2.1): the lower set of
+    threshold t is {f <= t} (eq (1)), so the thresholds cut the grey levels into k + 1 classes and a
+    pixel of value f is in class #{i : t_i < f}. Written out as that count (a comparison with every
+    threshold, summed), in row blocks to bound memory. Returns int32 labels of the image's shape."""
+    f = np.asarray(img).astype(np.int64)
+    t = np.asarray(thresholds_, dtype=np.int64).reshape(-1)
+    out = np.zeros(f.shape, np.int32)
+    if t.size == 0:
+        return out
+    f2 = f.reshape(f.shape[0], -1) if f.ndim > 1 else f.reshape(1, -1)
+    o2 = out.reshape(f2.shape)
+    for r in range(0, f2.shape[0], rows_per_step):
+        blk = f2[r:r + rows_per_step]
+        o2[r:r + rows_per_step] = (blk[..., None] > t[None, None, :]).sum(axis=-1)
+    return out

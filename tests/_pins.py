@@ -263,3 +263,38 @@ def pin_direct_dilation(lib=None, seeds=range(10)):
 
 ALL_PINS = [pin_golden, pin_threshold_rule, pin_closed_form_totals, pin_special_cases,
             pin_symmetries, pin_bounds, pin_alg1, pin_direct_dilation]
+
+
+# ------------------------------------------------------------------------------------------------
+# segmentation by the thresholds (Sec. 2.1: the lower set of t is {f <= t})
+
+def pin_segment():
+    """Hand cases, the library routine it reduces to, and invariants of the class labels."""
+    import oracle
+    # W1: f = [0, 4, 1] with threshold {2}: 0 and 1 lie in {f <= 2}, 4 does not
+    assert oracle.segment(np.array([[0, 4, 1]]), [2]).tolist() == [[0, 1, 0]]
+    # W2 with its threshold {3}
+    w2 = np.array([[0, 0, 5], [2, 7, 5]])
+    assert oracle.segment(w2, [3]).tolist() == [[0, 0, 1], [0, 1, 1]]
+    # a value equal to a threshold stays below it; two thresholds give three classes
+    assert oracle.segment(np.array([[2, 3, 4, 6, 7]]), [3, 6]).tolist() == [[0, 0, 1, 1, 2]]
+    # no thresholds: one class
+    assert oracle.segment(np.array([[0, 9, 255]]), []).tolist() == [[0, 0, 0]]
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        M = int(rng.integers(2, 300))
+        k = int(rng.integers(0, min(M, 12)))
+        thr = np.sort(rng.choice(M, size=k, replace=False))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 40)), int(rng.integers(1, 40))))
+        lab = oracle.segment(img, thr)
+        # the count of thresholds below f is numpy's left insertion point
+        assert np.array_equal(lab, np.searchsorted(thr, img, side="left"))
+        # labels grow with the value and stay in [0, k]
+        order = np.argsort(img, axis=None, kind="stable")
+        assert np.all(np.diff(lab.reshape(-1)[order]) >= 0)
+        assert lab.min() >= 0 and lab.max() <= k
+        # class i holds exactly the values in (t_i, t_{i+1}]
+        for i in range(k + 1):
+            lo = -1 if i == 0 else thr[i - 1]
+            hi = M if i == k else thr[i]
+            assert np.array_equal(lab == i, (img > lo) & (img <= hi))

@@ -42,3 +42,7 @@ def test_same_double_fixture_is_meaningful():
     from fractions import Fraction
     a, b = Fraction(1, 3), Fraction(333333333333333334, 10**18)
     assert a < b and float(a) == float(b)
+
+
+def test_segment_pins():
+    _pins.pin_segment()
