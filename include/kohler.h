@@ -173,6 +173,25 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
                     int32_t reps, kohler_plan *best, double *best_us);
 
 /*
+ * Segmentation by the thresholds (Sec. 2.1): the lower set of a threshold t is {f <= t} (eq (1)), so
+ * ascending thresholds t_1 < ... < t_k cut the grey levels into k + 1 classes, and the pixel of value
+ * f gets the label #{i : t_i < f} (0 .. k). Stream-ordered; every pointer is DEVICE memory:
+ *   d_img, dtype, H, W, pitch, M   the image as for kohler_curve (values >= M take label k)
+ *   d_thr            thresholds, strictly ascending in [0, M) (as kohler_curve_async writes them;
+ *                    otherwise the labels are unspecified), at least min(*d_n_thr, thr_capacity)
+ *   d_n_thr          one int32: how many thresholds there are (a count above thr_capacity, as a
+ *                    capacity-truncated curve call reports it, uses the first thr_capacity)
+ *   thr_capacity     0 .. M (host value)
+ *   d_labels         H rows of label_pitch elements (label_pitch >= W) of label_dtype: KOHLER_U8
+ *                    (needs thr_capacity <= 255) or KOHLER_U16
+ * Each pixel is read once and each label written once (one kernel launch, no allocation, no host
+ * synchronisation). Returns KOHLER_OK, KOHLER_E_ARG (checked on the host) or KOHLER_E_DEVICE.
+ */
+int kohler_segment(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                   int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
+                   void *d_labels, int label_dtype, int64_t label_pitch, kohler_stream_t stream);
+
+/*
  * ------------------------------------------------------------------------------------------------
  * Serving. A server runs a request loop on one context's device: callers submit images as they
  * arrive and collect each result by ticket. A scheduler thread admits queued requests in arrival

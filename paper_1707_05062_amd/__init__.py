@@ -146,6 +146,30 @@ class Context:
             raise KohlerError(st, "kohler_autotune")
         return best.as_dict(), float(us.value)
 
+    # -- segmentation ------------------------------------------------------------------------
+    def segment(self, img, thr, n_thr, capacity: int, M: int, out=None, label_dtype=None, stream=None):
+        """Enqueue the class labels of a device image for device thresholds `thr` (int32) and the
+        device count `n_thr` (an int32 tensor element, e.g. a curve call's ints[0:1]): label =
+        number of thresholds below the pixel value. Returns the label tensor (uint8 when the
+        capacity is at most 255, else uint16, unless label_dtype says otherwise)."""
+        torch = _torch()
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        if label_dtype is None:
+            label_dtype = torch.uint8 if capacity <= 255 else torch.uint16
+        lcode = _lib.U8 if label_dtype == torch.uint8 else _lib.U16
+        if out is None:
+            out = torch.empty((H, W), dtype=label_dtype, device=torch.device("cuda", self.device))
+        if out.dim() != 2 or out.stride(1) != 1 or tuple(out.shape) != (H, W):
+            raise ValueError("labels must be an H x W tensor with unit column stride")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = self._lib.kohler_segment(self._h, ctypes.c_void_p(ptr), code, H, W, pitch, M, _ptr(thr),
+                                      ctypes.c_void_p(n_thr.data_ptr()), int(capacity), _ptr(out), lcode,
+                                      out.stride(0) if H > 1 else W, ctypes.c_void_p(s.cuda_stream))
+        del keep
+        if st != OK:
+            raise KohlerError(st, "kohler_segment")
+        return out
+
     # -- synchronous -------------------------------------------------------------------------
     def curve(self, img, M: int, nbhd: int = 4, capacity: int | None = None,
               check: bool = True) -> CurveResult:

@@ -14,7 +14,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libkohler.so")
 
-SOURCES = ["kohler_kernels.hip", "kohler_api.cpp", "kohler_server.cpp"]
+SOURCES = ["kohler_kernels.hip", "kohler_api.cpp", "kohler_server.cpp", "kohler_segment.hip"]
 HEADERS = ["kohler_impl.h", "kohler_host.h"]
 
 HIPCC_FLAGS = [
