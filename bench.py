@@ -9,6 +9,7 @@ copies (32 x 17.9 MB = 573 MB) so that the 256 MB Infinity Cache cannot serve th
 comes from the library's autotuner, run on the image before timing (or from --plan).
 
 Also measured in the same run (reported beside the headline, not as separate lines):
+  segment  the labels of the same image by its thresholds (a read-once, write-once stream);
   batched  96 uint8 images of log-uniform sizes (128^2 .. 4000x3000) in one persistent launch vs the
            plain kernel launched once per image on one stream;
   served   a Poisson stream of 240 requests/s (70% 1080p video frames, 20% 4K frames, 10% 18 MP
@@ -176,6 +177,8 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
         torch.cuda.synchronize()
         log(f"copy probe: {len(bufs)} copies of {src.numel()} bytes")
 
+    seg = segment_stream(args, ctx, torch, bufs, outs, img, M) if args.only != "curve" else None
+
     npx = H * W
     alg_bytes = npx * 1 + 3 * M * 8 + 4 * n_thr + 12  # pixels read once + curve and thresholds written
     achieved = alg_bytes / kern / 1e9
@@ -203,10 +206,44 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
         "traffic_source": traffic["source"] if traffic else
             "null: no hardware-counter measurement for this kernel build and plan",
         "selfcheck": selfcheck,
+        "segment": seg,
         "H": H, "W": W, "M": M, "nbhd": nbhd, "rotate_buffers": len(bufs),
     }
     del bufs
     return res, img
+
+
+# ------------------------------------------------------------------------------------------------
+# segmentation of the same image by its thresholds: a read-once, write-once stream
+
+def segment_stream(args, ctx, torch, bufs, outs, img, M) -> dict:
+    H, W = img.shape
+    n = int(outs["ints"][0])
+    cap = min(outs["thr"].numel(), 255)  # u8 labels: at most 255 thresholds (M = 256 has at most 128)
+    labs = [torch.empty((H, W), dtype=torch.uint8, device=bufs[0].device) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    ctx.segment(bufs[0], outs["thr"], outs["ints"][0:1], cap, M, out=labs[0])
+    torch.cuda.synchronize()
+    thr = outs["thr"][:n].cpu().numpy()
+    check = bool(np.array_equal(labs[0].cpu().numpy(), np.searchsorted(thr, img, side="left")))
+    for i in range(args.warmup):
+        ctx.segment(bufs[i % len(bufs)], outs["thr"], outs["ints"][0:1], cap, M, out=labs[i % 2])
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(args.steps):
+        ctx.segment(bufs[i % len(bufs)], outs["thr"], outs["ints"][0:1], cap, M, out=labs[i % 2])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / args.steps
+    nbytes = 2 * H * W  # each u8 pixel read once, each u8 label written once
+    log(f"segment: {t*1e6:.2f} us per launch, {nbytes / t / 1e9:.0f} GB/s, labels match: {check}")
+    return {"workload": f"labels of the {H}x{W} image by its {n} thresholds (u8 in, u8 labels)",
+            "kernel_us": t * 1e6, "gpixel_s": H * W / t / 1e9,
+            "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": nbytes},
+            "labels_match_searchsorted": check}
 
 
 # ------------------------------------------------------------------------------------------------
@@ -434,10 +471,11 @@ def run(args) -> dict:
         "frame_ms": head["frame_ms"],
         "roofline": head["roofline"],
         "selfcheck": head["selfcheck"],
+        "segment": head["segment"],
         "paper_context": {"fast_A_gpixel_s": 0.138, "hardware": "Intel i7-4702HQ 4C/8T",
                           "image": "3672x4896 photograph (Table 1)"},
     }
-    if args.only != "headline":
+    if args.only == "all":
         result["batched"] = batched(args, K, ctx, torch, gen)
         result["served"] = served(args, K, ctx, torch, gen)
     if not args.no_cpu_baseline:
@@ -455,7 +493,8 @@ def main():
     ap.add_argument("--rotate", type=int, default=32, help="distinct input buffers cycled by the steps")
     ap.add_argument("--plan", default="", help="fixed plan form:band:block:grid:px_per_lane:replicas "
                                                "instead of autotuning")
-    ap.add_argument("--only", choices=["all", "headline"], default="all")
+    ap.add_argument("--only", choices=["all", "headline", "curve"], default="all",
+                    help="headline: the curve and the segmentation of the 18 MP image only; curve: the curve only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after timing, copy each input buffer once (a reference for byte counters)")
