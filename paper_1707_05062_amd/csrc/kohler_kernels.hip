@@ -41,6 +41,8 @@ namespace {
 
 constexpr int kRowBatch = 4;  // rows whose loads a wave issues together before using them
 constexpr int kChunk = 4;     // units (rows of a strip) a wave claims at a time
+constexpr int kTailRows = 2;  // rows of the pieces a workgroup's last chunks are claimed in
+static_assert(kChunk % kTailRows == 0, "a chunk splits into whole pieces");
 
 // Explicit address spaces keep loads, stores and atomics on the global (not flat) and LDS paths.
 #define KOHLER_GLOBAL __attribute__((address_space(1)))
@@ -1285,11 +1287,26 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
             // chunk numbers stay below 2^32 (at most 2^40 pixels, chunks of kChunk rows by at least 256
             // columns),
             // so the decode is a 32-bit division by a wave-uniform value
-            for (uint32_t j = claim(); j < mine; j = claim()) {
-                const uint32_t c = (uint32_t)g + j * (uint32_t)G;
+            //
+            // The workgroup's last chunks are claimed in pieces of kTailRows rows (a quarter of its
+            // waves' worth of chunks), so that its waves finish closer together.
+            const uint32_t ntail = (uint32_t)min<int64_t>(mine, (int64_t)(blockDim.x >> 8));
+            const uint32_t whole = (uint32_t)mine - ntail;
+            constexpr uint32_t kPieces = kChunk / kTailRows;
+            const uint32_t nclaims = whole + ntail * kPieces;
+            for (uint32_t j = claim(); j < nclaims; j = claim()) {
+                uint32_t jc = j, off = 0, len = kChunk;
+                if (j >= whole) {
+                    jc = whole + (j - whole) / kPieces;
+                    off = ((j - whole) % kPieces) * kTailRows;
+                    len = kTailRows;
+                }
+                const uint32_t c = (uint32_t)g + jc * (uint32_t)G;
                 const uint32_t blk = c / (uint32_t)ns, strip = c - blk * (uint32_t)ns;
-                const int64_t r0 = (int64_t)blk * kChunk;
-                strip_range<Pix, NB, K, CLAMP>(im, (int)strip, r0, min(im.H, r0 + kChunk), mm1, acc, spill, vm);
+                const int64_t r0 = (int64_t)blk * kChunk + off;
+                if (r0 < im.H)  // a piece past the last row of a short final row block is empty
+                    strip_range<Pix, NB, K, CLAMP>(im, (int)strip, r0, min(im.H, r0 + (int64_t)len), mm1, acc,
+                                                   spill, vm);
             }
         });
         // units of this workgroup: kChunk rows per chunk, less the short chunks of the last row block
