@@ -6,8 +6,9 @@ product path (the HIP library and its Python binding) never does, and it shares 
 Reference: G. Noyel, arXiv 1707.05062. ``curve`` is the definition of Sec. 2.1 (eqs (1)-(3)) written
 out over every threshold and every ordered neighbour pair; ``alg1`` is Algorithm 1 of Sec. 3.1 over
 the half neighbourhood of Sec. 3.2; ``thresholds`` gives the curve's local maxima and the optimum of
-eq (4); ``segment`` labels pixels by the classes those thresholds cut (Sec. 2.1). The C sources are
-in ``kohler_oracle.c``; ``build()`` compiles them with gcc and OpenMP.
+eq (4); ``segment`` labels pixels by the classes those thresholds cut (Sec. 2.1), ``class_stats`` and
+``mean_image`` give each class's mean value, ``top_thresholds`` the most significant thresholds. The
+C sources are in ``kohler_oracle.c``; ``build()`` compiles them with gcc and OpenMP.
 """
 from __future__ import annotations
 
@@ -147,3 +148,48 @@ def segment(img: np.ndarray, thresholds_, rows_per_step: int = 256) -> np.ndarra
         blk = f2[r:r + rows_per_step]
         o2[r:r + rows_per_step] = (blk[..., None] > t[None, None, :]).sum(axis=-1)
     return out
+
+
+def class_stats(img: np.ndarray, thresholds_, M: int):
+    """Per-class pixel count, value sum and mean for the k + 1 classes that ascending thresholds cut
+    (Sec. 2.1, where each class of Fig. 1 is shown at the mean value of its pixels; class of a pixel
+    as in ``segment``). A value of M or more counts in class k with the
+    value M. Written out class by class: count = number of pixels with that label, sum = their values
+    added in int64, mean = sum / count as one float64 division (0.0 for an empty class). Returns
+    (int64 count[k+1], int64 sum[k+1], float64 mean[k+1])."""
+    f = np.minimum(np.asarray(img).astype(np.int64), M)
+    lab = segment(f, thresholds_)
+    k = len(np.asarray(thresholds_).reshape(-1))
+    count = np.zeros(k + 1, np.int64)
+    total = np.zeros(k + 1, np.int64)
+    mean = np.zeros(k + 1, np.float64)
+    for j in range(k + 1):
+        sel = lab == j
+        count[j] = int(sel.sum())
+        total[j] = int(f[sel].sum(dtype=np.int64))
+        if count[j]:
+            mean[j] = np.float64(total[j]) / np.float64(count[j])
+    return count, total, mean
+
+
+def mean_image(img: np.ndarray, thresholds_, M: int) -> np.ndarray:
+    """Every pixel replaced by the mean of its class (``class_stats``), rounded to the nearest
+    integer with ties to even, in the image's own dtype."""
+    img = np.asarray(img)
+    _, _, mean = class_stats(img, thresholds_, M)
+    lab = segment(np.minimum(img.astype(np.int64), M), thresholds_)
+    return np.rint(mean)[lab].astype(img.dtype)
+
+
+def top_thresholds(sum_, count, thresholds_, k: int):
+    """The k most significant thresholds (Sec. 2.1, the discussion of Fig. 1; the paper does not define
+    "most significant", so this takes the reading: largest contrast first): the thresholds ordered by C(t) = sum(t) / count(t)
+    descending (0 where count is 0), compared as exact rationals, equal C in ascending t; the first
+    min(k, n) of that order."""
+    from fractions import Fraction
+
+    def key(t):
+        c = int(count[t])
+        return (-(Fraction(int(sum_[t]), c) if c else Fraction(0)), int(t))
+
+    return [int(t) for t in sorted((int(t) for t in thresholds_), key=key)[:max(0, k)]]

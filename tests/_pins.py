@@ -298,3 +298,74 @@ def pin_segment():
             lo = -1 if i == 0 else thr[i - 1]
             hi = M if i == k else thr[i]
             assert np.array_equal(lab == i, (img > lo) & (img <= hi))
+
+
+def pin_class_stats():
+    """Class counts, sums and means by hand, by brute force over pixels and by invariants; the mean
+    image; the most significant thresholds by hand and against a float sort where C values are far
+    apart."""
+    import oracle
+    # W1 = [0, 4, 1], threshold {2}: class 0 holds 0 and 1, class 1 holds 4
+    c, s, m = oracle.class_stats(np.array([[0, 4, 1]]), [2], 5)
+    assert c.tolist() == [2, 1] and s.tolist() == [1, 4] and m.tolist() == [0.5, 4.0]
+    # the class means 0.5 and 4.0 round to 0 (ties to even) and 4
+    assert oracle.mean_image(np.array([[0, 4, 1]], np.uint8), [2], 5).tolist() == [[0, 4, 0]]
+    # an empty middle class has mean 0; a value >= M counts in the top class as M
+    c, s, m = oracle.class_stats(np.array([[1, 9, 300]]), [3, 5], 256)
+    assert c.tolist() == [1, 0, 2] and s.tolist() == [1, 0, 265] and m.tolist() == [1.0, 0.0, 132.5]
+    # no thresholds: one class, the image mean
+    c, s, m = oracle.class_stats(np.array([[2, 3], [4, 7]]), [], 8)
+    assert c.tolist() == [4] and s.tolist() == [16] and m.tolist() == [4.0]
+    rng = np.random.default_rng(11)
+    for _ in range(20):
+        M = int(rng.integers(2, 300))
+        k = int(rng.integers(0, min(M, 12)))
+        thr = np.sort(rng.choice(M, size=k, replace=False))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 30)), int(rng.integers(1, 30))))
+        c, s, m = oracle.class_stats(img, thr, M)
+        # brute force: walk the pixels, find each one's class by scanning the thresholds
+        bc = [0] * (k + 1)
+        bs = [0] * (k + 1)
+        for v in img.reshape(-1).tolist():
+            j = 0
+            while j < k and thr[j] < v:
+                j += 1
+            bc[j] += 1
+            bs[j] += v
+        assert c.tolist() == bc and s.tolist() == bs
+        # invariants: every pixel counted once, the class means weighted by counts give the image sum,
+        # and a non-empty class's mean lies inside its interval (t_{j-1}, t_j]
+        assert c.sum() == img.size and s.sum() == img.sum()
+        for j in range(k + 1):
+            if c[j]:
+                lo = -1 if j == 0 else thr[j - 1]
+                hi = M - 1 if j == k else thr[j]
+                assert lo < m[j] <= hi
+                assert abs(m[j] * c[j] - s[j]) <= 1e-9 * max(1, s[j])
+            else:
+                assert m[j] == 0.0
+        mi = oracle.mean_image(img.astype(np.uint16), thr, M)
+        lab = oracle.segment(img, thr)
+        assert np.array_equal(mi, np.rint(m)[lab].astype(np.uint16))
+
+    # most significant thresholds: C = [0, 3/2, 1, 3/2, 2, 0]; the maxima 1 and 4 (and 3) in order of C
+    s_ = np.array([0, 3, 2, 3, 4, 0])
+    k_ = np.array([1, 2, 2, 2, 2, 0])
+    assert oracle.top_thresholds(s_, k_, [1, 3, 4], 2) == [4, 1]   # 2 first, then the tie 1 < 3
+    assert oracle.top_thresholds(s_, k_, [1, 3, 4], 5) == [4, 1, 3]
+    assert oracle.top_thresholds(s_, k_, [1, 3, 4], 0) == []
+    assert oracle.top_thresholds(s_, k_, [5, 1], 2) == [1, 5]      # count 0 reads as C = 0
+    # exact order where the doubles tie: 2^53 and 2^53 + 1 (over 1) are one double, so a float
+    # comparison would fall back to the smaller t
+    big = np.array([2 ** 53, 2 ** 53 + 1], dtype=np.int64)
+    assert oracle.top_thresholds(big, np.array([1, 1]), [0, 1], 1) == [1]
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        n = int(rng.integers(1, 40))
+        cnt = rng.integers(2, 1000, size=n)
+        C = rng.permutation(n).astype(np.float64) + 0.5     # distinct, at least 1 apart
+        sm = np.rint(C * cnt).astype(np.int64)               # sum / count within 1/4 of C
+        thr = sorted(rng.choice(n, size=int(rng.integers(0, n + 1)), replace=False).tolist())
+        kk = int(rng.integers(0, n + 2))
+        want = sorted(thr, key=lambda t: -C[t])[:kk]
+        assert oracle.top_thresholds(sm, cnt, thr, kk) == want

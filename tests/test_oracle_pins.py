@@ -46,3 +46,7 @@ def test_same_double_fixture_is_meaningful():
 
 def test_segment_pins():
     _pins.pin_segment()
+
+
+def test_class_stats_pins():
+    _pins.pin_class_stats()
