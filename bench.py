@@ -239,11 +239,47 @@ def segment_stream(args, ctx, torch, bufs, outs, img, M) -> dict:
     t = e0.elapsed_time(e1) * 1e-3 / args.steps
     nbytes = 2 * H * W  # each u8 pixel read once, each u8 label written once
     log(f"segment: {t*1e6:.2f} us per launch, {nbytes / t / 1e9:.0f} GB/s, labels match: {check}")
+
+    # class statistics (histogram + fold) and the class-mean image, same image and thresholds
+    n_dev = outs["ints"][0:1]
+    means = []
+
+    def timed(fn):
+        for i in range(args.warmup):
+            fn(i)
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for i in range(args.steps):
+            fn(i)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) * 1e-3 / args.steps
+
+    def stats(i):
+        means[:] = [ctx.class_stats(bufs[i % len(bufs)], outs["thr"], n_dev, cap, M)]
+
+    ts = timed(stats)
+    cnt, tot, mean = [x.cpu().numpy() for x in means[0]]
+    lab = np.searchsorted(thr, img, side="left").reshape(-1)
+    want_cnt = np.bincount(lab, minlength=n + 1)
+    want_tot = np.bincount(lab, weights=img.reshape(-1).astype(np.float64), minlength=n + 1).astype(np.int64)
+    stats_ok = bool(np.array_equal(cnt[:n + 1], want_cnt) and np.array_equal(tot[:n + 1], want_tot))
+    mimgs = [torch.empty_like(bufs[0]) for _ in range(2)]
+    tm = timed(lambda i: ctx.mean_image(bufs[i % len(bufs)], outs["thr"], n_dev, cap, M, means[0][2],
+                                        out=mimgs[i % 2]))
+    mean_ok = bool(np.array_equal(mimgs[(args.steps - 1) % 2].cpu().numpy(),
+                                  np.rint(mean[:n + 1])[lab].reshape(img.shape).astype(np.uint8)))
+    log(f"class stats: {ts*1e6:.2f} us ({H * W / ts / 1e9:.0f} GB/s), match {stats_ok}; "
+        f"class-mean image: {tm*1e6:.2f} us ({nbytes / tm / 1e9:.0f} GB/s), match {mean_ok}")
     return {"workload": f"labels of the {H}x{W} image by its {n} thresholds (u8 in, u8 labels)",
             "kernel_us": t * 1e6, "gpixel_s": H * W / t / 1e9,
             "roofline": {"bound": "hbm", "achieved": nbytes / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": nbytes},
-            "labels_match_searchsorted": check}
+            "labels_match_searchsorted": check,
+            "class_stats_us": ts * 1e6, "class_stats_gb_s": H * W / ts / 1e9, "class_stats_match": stats_ok,
+            "mean_image_us": tm * 1e6, "mean_image_gb_s": nbytes / tm / 1e9, "mean_image_match": mean_ok}
 
 
 # ------------------------------------------------------------------------------------------------

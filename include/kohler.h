@@ -191,6 +191,61 @@ int kohler_segment(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int
                    int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
                    void *d_labels, int label_dtype, int64_t label_pitch, kohler_stream_t stream);
 
+/* Largest thr_capacity kohler_class_stats takes (its per-class sums are kept on chip). */
+#define KOHLER_MAX_CLASS_THRESHOLDS 8000
+
+/*
+ * Class statistics of the segmentation by the thresholds (Sec. 2.1, where each class of Fig. 1 is
+ * shown at the mean value of its pixels). Class j holds the pixels with label j as kohler_segment
+ * gives it; a value of M or more counts in class k with the value M. Stream-ordered; every pointer is
+ * DEVICE memory; image and thresholds as for kohler_segment, with thr_capacity <=
+ * KOHLER_MAX_CLASS_THRESHOLDS.
+ *   d_count, d_sum   int64[thr_capacity + 1]: pixels and sum of their values per class
+ *   d_mean           double[thr_capacity + 1]: sum / count, one correctly rounded division, 0.0 for
+ *                    an empty class
+ * Entries past the n + 1 classes in use are 0. Two kernel launches: a grey-level histogram (each
+ * pixel read once) into a context scratch array, then one workgroup that folds it into the classes
+ * and clears it; calls on one context must not overlap on the device (they share that array).
+ * Allocates the scratch on the first call. Returns KOHLER_OK, KOHLER_E_ARG, KOHLER_E_NOMEM or
+ * KOHLER_E_DEVICE.
+ */
+int kohler_class_stats(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                       int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
+                       int64_t *d_count, int64_t *d_sum, double *d_mean, kohler_stream_t stream);
+
+/*
+ * The class-mean image (Sec. 2.1: the image simplified to one grey level per class, each class at
+ * the mean value of its pixels): every pixel replaced by the mean of its class, rounded to the
+ * nearest integer with ties to even, in the image's own type. Stream-ordered, DEVICE pointers:
+ *   d_img .. thr_capacity   as for kohler_segment
+ *   d_mean           double[thr_capacity + 1] class means (kohler_class_stats' d_mean); a value of
+ *                    M or more takes class n's mean
+ *   d_out, out_pitch H rows of out_pitch >= W elements of the image's type
+ * One kernel launch, each pixel read once and written once. Returns KOHLER_OK, KOHLER_E_ARG or
+ * KOHLER_E_DEVICE.
+ */
+int kohler_mean_image(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                      int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
+                      const double *d_mean, void *d_out, int64_t out_pitch, kohler_stream_t stream);
+
+/*
+ * The k most significant thresholds (Sec. 2.1, the discussion of Fig. 1, which keeps the 6 most
+ * significant local maxima; read here as the thresholds of largest contrast C): the thresholds
+ * ordered by C(t) = sum(t) / count(t) descending, compared exactly (128-bit cross products), equal C
+ * in ascending t; the first min(k, n) of that order. Stream-ordered, DEVICE pointers:
+ *   d_sum, d_count   int64[M]: a curve (kohler_curve_async's outputs)
+ *   d_thr, d_n_thr, thr_capacity   strictly ascending thresholds and their count, as for
+ *                    kohler_segment; a threshold outside [0, M) counts as C = 0
+ *   k                host value >= 0
+ *   d_top            int32[k]: the selected thresholds, most significant first
+ *   d_n_top          one int32: min(k, n)
+ * One workgroup (each threshold's exact rank among the n, O(n^2) comparisons). Returns KOHLER_OK,
+ * KOHLER_E_ARG or KOHLER_E_DEVICE.
+ */
+int kohler_top_thresholds(kohler_ctx *ctx, const int64_t *d_sum, const int64_t *d_count, int32_t M,
+                          const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity, int32_t k,
+                          int32_t *d_top, int32_t *d_n_top, kohler_stream_t stream);
+
 /*
  * ------------------------------------------------------------------------------------------------
  * Serving. A server runs a request loop on one context's device: callers submit images as they

@@ -170,6 +170,59 @@ class Context:
             raise KohlerError(st, "kohler_segment")
         return out
 
+    def class_stats(self, img, thr, n_thr, capacity: int, M: int, stream=None):
+        """Enqueue the per-class pixel count, value sum and mean (device tensors of capacity + 1
+        entries: int64, int64, float64) of a device image for the device thresholds `thr` and count
+        `n_thr`, classes as in `segment`."""
+        torch = _torch()
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        dev = torch.device("cuda", self.device)
+        count = torch.empty(capacity + 1, dtype=torch.int64, device=dev)
+        total = torch.empty(capacity + 1, dtype=torch.int64, device=dev)
+        mean = torch.empty(capacity + 1, dtype=torch.float64, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = self._lib.kohler_class_stats(self._h, ctypes.c_void_p(ptr), code, H, W, pitch, M, _ptr(thr),
+                                          ctypes.c_void_p(n_thr.data_ptr()), int(capacity), _ptr(count),
+                                          _ptr(total), _ptr(mean), ctypes.c_void_p(s.cuda_stream))
+        del keep
+        if st != OK:
+            raise KohlerError(st, "kohler_class_stats")
+        return count, total, mean
+
+    def mean_image(self, img, thr, n_thr, capacity: int, M: int, mean, out=None, stream=None):
+        """Enqueue the class-mean image (each pixel replaced by its class's mean rounded to nearest,
+        ties to even, in the image's dtype) for class means `mean` (float64 device tensor)."""
+        torch = _torch()
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        if out is None:
+            out = torch.empty((H, W), dtype=img.dtype, device=torch.device("cuda", self.device))
+        if out.dim() != 2 or out.stride(1) != 1 or tuple(out.shape) != (H, W) or out.dtype != img.dtype:
+            raise ValueError("the output must be an H x W tensor of the image's dtype with unit column stride")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = self._lib.kohler_mean_image(self._h, ctypes.c_void_p(ptr), code, H, W, pitch, M, _ptr(thr),
+                                         ctypes.c_void_p(n_thr.data_ptr()), int(capacity), _ptr(mean), _ptr(out),
+                                         out.stride(0) if H > 1 else W, ctypes.c_void_p(s.cuda_stream))
+        del keep
+        if st != OK:
+            raise KohlerError(st, "kohler_mean_image")
+        return out
+
+    def top_thresholds(self, sum_, count, thr, n_thr, capacity: int, M: int, k: int, stream=None):
+        """Enqueue the k most significant thresholds (largest C first, equal C in ascending t) of a
+        device curve (`sum_`, `count`: int64[M]) and its device thresholds. Returns (top int32[k],
+        n_top int32[1]) device tensors."""
+        torch = _torch()
+        dev = torch.device("cuda", self.device)
+        top = torch.empty(max(k, 1), dtype=torch.int32, device=dev)
+        n_top = torch.empty(1, dtype=torch.int32, device=dev)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        st = self._lib.kohler_top_thresholds(self._h, _ptr(sum_), _ptr(count), M, _ptr(thr),
+                                             ctypes.c_void_p(n_thr.data_ptr()), int(capacity), int(k), _ptr(top),
+                                             _ptr(n_top), ctypes.c_void_p(s.cuda_stream))
+        if st != OK:
+            raise KohlerError(st, "kohler_top_thresholds")
+        return top, n_top
+
     # -- synchronous -------------------------------------------------------------------------
     def curve(self, img, M: int, nbhd: int = 4, capacity: int | None = None,
               check: bool = True) -> CurveResult:

@@ -15,6 +15,7 @@ MAX_M_U16 = 10200
 EXPORTS = (
     "kohler_create", "kohler_destroy", "kohler_strerror", "kohler_curve", "kohler_curve_async",
     "kohler_curve_batch", "kohler_set_plan", "kohler_get_plan", "kohler_autotune", "kohler_segment",
+    "kohler_class_stats", "kohler_mean_image", "kohler_top_thresholds",
     "kohler_server_create", "kohler_server_destroy", "kohler_server_submit", "kohler_server_poll",
     "kohler_server_wait", "kohler_server_cancel", "kohler_server_pause", "kohler_server_stats",
 )
@@ -94,6 +95,12 @@ def load(path: str = LIB_PATH):
     lib.kohler_segment.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, i32, vp, vp, i32, vp, ctypes.c_int,
                                    i64, vp]
     lib.kohler_segment.restype = ctypes.c_int
+    lib.kohler_class_stats.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, i32, vp, vp, i32, vp, vp, vp, vp]
+    lib.kohler_class_stats.restype = ctypes.c_int
+    lib.kohler_mean_image.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, i32, vp, vp, i32, vp, vp, i64, vp]
+    lib.kohler_mean_image.restype = ctypes.c_int
+    lib.kohler_top_thresholds.argtypes = [vp, vp, vp, i32, vp, vp, i32, i32, vp, vp, vp]
+    lib.kohler_top_thresholds.restype = ctypes.c_int
     u64 = ctypes.c_uint64
     lib.kohler_server_create.argtypes = [vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.kohler_server_create.restype = ctypes.c_int

@@ -200,6 +200,7 @@ void kohler_destroy(kohler_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(ctx->acc1);
+    (void)hipFree(ctx->level_hist);
     (void)hipFree(ctx->done1);
     (void)hipFree(ctx->rflag1);
     (void)hipFree(ctx->accb);

@@ -47,6 +47,9 @@ struct kohler_ctx {
     int32_t *h_thr = nullptr;
     int32_t h_thr_cap = 0;
 
+    // class statistics: grey-level histogram (kMaxM + 1 words), allocated on first use, zero between calls
+    unsigned long long *level_hist = nullptr;
+
     std::map<std::tuple<int, int, int>, kohler_plan> plans;
     std::mutex mu;
 };

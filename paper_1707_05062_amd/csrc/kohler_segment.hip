@@ -1,11 +1,22 @@
-// Segmentation by the thresholds of the contrast curve (G. Noyel, arXiv 1707.05062, Sec. 2.1): the
-// lower set of a threshold t is {f <= t} (eq (1)), so ascending thresholds t_1 < ... < t_k cut the
-// grey levels into k + 1 classes, and a pixel of value f is labelled #{i : t_i < f}.
+// Consumers of the contrast curve's thresholds (G. Noyel, arXiv 1707.05062, Sec. 2.1): the lower set
+// of a threshold t is {f <= t} (eq (1)), so ascending thresholds t_1 < ... < t_k cut the grey levels
+// into k + 1 classes, and a pixel of value f is in class #{i : t_i < f}. Each class of the paper's
+// Fig. 1 is shown at the mean value of its pixels, and its thresholds are the most significant
+// maxima of the curve.
 //
-// The kernel is a stream over the image: every workgroup first builds a label table for the M grey
-// levels in LDS (thresholds copied to LDS, one binary search per level), then maps pixels through it,
-// 16 bytes of input per lane and step, with loads of several steps in flight. Each pixel is read
-// once and its label written once; the entry point kohler_segment is declared in include/kohler.h.
+//   segment_kernel     labels (or class means) of every pixel: a stream over the image; every
+//                      workgroup first builds a table for the M + 1 grey levels in LDS (one binary
+//                      search per level over the thresholds in LDS; level M stands for every value
+//                      >= M), then maps pixels through it, 16 bytes of input per lane and step, with
+//                      loads of several steps in flight. Each pixel is read once and written once.
+//   level_hist_kernel  the image's grey-level histogram (same stream shape, LDS counters per
+//                      workgroup, one global atomic per non-empty level and workgroup)
+//   class_stats_kernel one workgroup: folds the histogram into per-class count, sum and mean, and
+//                      clears the histogram for the next call
+//   top_kernel         one workgroup: the k thresholds of largest C, by exact rank
+//
+// The entry points (kohler_segment, kohler_class_stats, kohler_mean_image, kohler_top_thresholds) are
+// declared in include/kohler.h.
 
 #include <hip/hip_runtime.h>
 
@@ -34,25 +45,38 @@ struct SegParams {
     int32_t M, cap;
     int32_t flat;  // 1: input and output rows are contiguous (pitch == W) and 16-byte aligned
     int32_t pad;
+    const double *mean;  // non-null: the table holds each class's rounded mean instead of its label
 };
 
 typedef uint32_t seg_u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename Pout>
-__device__ __forceinline__ uint32_t lut_of(const KOHLER_SEG_LDS Pout *lut, uint32_t v, uint32_t Mm1) {
-    return (uint32_t)lut[min(v, Mm1)];  // values past M - 1 take the top level's label
+__device__ __forceinline__ uint32_t lut_of(const KOHLER_SEG_LDS Pout *lut, uint32_t v, uint32_t Mtop) {
+    return (uint32_t)lut[min(v, Mtop)];  // entry M stands for every value >= M
+}
+
+// Number of thresholds below v among the n ascending ones at thr (first index with thr[i] >= v).
+template <class T>
+__device__ __forceinline__ int rank_below(const T *thr, int n, int v) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (thr[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // Labels of the 16 input bytes of one group, packed as the output row holds them.
 template <typename Pin, typename Pout>
-__device__ __forceinline__ void map_group(const seg_u32x4 in, const KOHLER_SEG_LDS Pout *lut, uint32_t Mm1,
+__device__ __forceinline__ void map_group(const seg_u32x4 in, const KOHLER_SEG_LDS Pout *lut, uint32_t Mtop,
                                           Pout (&o)[16 / sizeof(Pin)]) {
     constexpr int PPW = 4 / (int)sizeof(Pin);  // pixels per input word
     constexpr uint32_t MASK = sizeof(Pin) == 1 ? 0xFFu : 0xFFFFu;
 #pragma unroll
     for (int w = 0; w < 4; ++w)
 #pragma unroll
-        for (int k = 0; k < PPW; ++k) o[w * PPW + k] = (Pout)lut_of(lut, (in[w] >> (8 * (int)sizeof(Pin) * k)) & MASK, Mm1);
+        for (int k = 0; k < PPW; ++k) o[w * PPW + k] = (Pout)lut_of(lut, (in[w] >> (8 * (int)sizeof(Pin) * k)) & MASK, Mtop);
 }
 
 template <typename Pin, typename Pout>
@@ -60,23 +84,18 @@ __global__ void __launch_bounds__(kSegBlock) segment_kernel(SegParams p) {
     extern __shared__ __align__(16) uint8_t seg_lds[];
     KOHLER_SEG_LDS uint8_t *lbase = (KOHLER_SEG_LDS uint8_t *)seg_lds;
     KOHLER_SEG_LDS Pout *lut = reinterpret_cast<KOHLER_SEG_LDS Pout *>(lbase);  // M labels
-    KOHLER_SEG_LDS int32_t *thr =
-        reinterpret_cast<KOHLER_SEG_LDS int32_t *>(lbase + ((p.M * sizeof(Pout) + 15) & ~(size_t)15));  // cap
+    KOHLER_SEG_LDS int32_t *thr = reinterpret_cast<KOHLER_SEG_LDS int32_t *>(
+        lbase + (((size_t)(p.M + 1) * sizeof(Pout) + 15) & ~(size_t)15));  // cap
 
     const int n = min(max(*p.n_thr, 0), p.cap);  // thresholds in use (a capacity-truncated list too)
     for (int i = threadIdx.x; i < n; i += blockDim.x) thr[i] = p.thr[i];
     __syncthreads();
-    for (int v = threadIdx.x; v < p.M; v += blockDim.x) {
-        int lo = 0, hi = n;  // number of thresholds below v: first index with thr[i] >= v
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (thr[mid] < v) lo = mid + 1;
-            else hi = mid;
-        }
-        lut[v] = (Pout)lo;
+    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
+        const int j = rank_below(thr, n, v);
+        lut[v] = p.mean ? (Pout)__builtin_rint(p.mean[j]) : (Pout)j;  // ties to even
     }
     __syncthreads();
-    const uint32_t Mm1 = (uint32_t)p.M - 1u;
+    const uint32_t Mtop = (uint32_t)p.M;  // index of the table's last entry
 
     if (p.flat) {
         // the image as one array of N pixels, in 16-byte groups of G pixels
@@ -98,7 +117,7 @@ __global__ void __launch_bounds__(kSegBlock) segment_kernel(SegParams p) {
                 const int64_t g = g0 + (int64_t)u * kSegBlock;
                 if (g < ngroups) {
                     Pout o[G];
-                    map_group<Pin, Pout>(in[u], lut, Mm1, o);
+                    map_group<Pin, Pout>(in[u], lut, Mtop, o);
                     // G labels, packed into NW 32-bit words: 32, 16 or 8 bytes per group
                     constexpr int LPW = 4 / (int)sizeof(Pout);
                     constexpr int NW = G / LPW;
@@ -126,15 +145,146 @@ __global__ void __launch_bounds__(kSegBlock) segment_kernel(SegParams p) {
         const int64_t tail = ngroups * G;
         const KOHLER_SEG_GLOBAL Pin *s1 = (const KOHLER_SEG_GLOBAL Pin *)p.img;
         for (int64_t i = tail + (int64_t)blockIdx.x * kSegBlock + threadIdx.x; i < N; i += (int64_t)gridDim.x * kSegBlock)
-            dst[i] = (Pout)lut_of(lut, (uint32_t)s1[i], Mm1);
+            dst[i] = (Pout)lut_of(lut, (uint32_t)s1[i], Mtop);
     } else {
         // rows with a pitch: one pixel per lane and step
         const KOHLER_SEG_GLOBAL Pin *src = (const KOHLER_SEG_GLOBAL Pin *)p.img;
         KOHLER_SEG_GLOBAL Pout *dst = (KOHLER_SEG_GLOBAL Pout *)p.out;
         for (int64_t r = blockIdx.x; r < p.H; r += gridDim.x)
             for (int64_t c = threadIdx.x; c < p.W; c += kSegBlock)
-                dst[r * p.out_pitch + c] = (Pout)lut_of(lut, (uint32_t)src[r * p.pitch + c], Mm1);
+                dst[r * p.out_pitch + c] = (Pout)lut_of(lut, (uint32_t)src[r * p.pitch + c], Mtop);
     }
+}
+
+// Grey-level histogram of the image into hist[0..M] (entry M counts every value >= M), added to
+// what hist holds. Per workgroup: LDS counters (32 bits: a workgroup sees fewer than 2^32 pixels),
+// then one device-scope atomic per non-empty level.
+template <typename Pin>
+__global__ void __launch_bounds__(kSegBlock) level_hist_kernel(SegParams p, unsigned long long *hist) {
+    extern __shared__ __align__(16) uint8_t seg_lds[];
+    KOHLER_SEG_LDS uint32_t *h = (KOHLER_SEG_LDS uint32_t *)seg_lds;  // M + 1 counters
+    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) h[v] = 0u;
+    __syncthreads();
+    const uint32_t Mtop = (uint32_t)p.M;
+    auto count = [&](uint32_t v) {
+        __hip_atomic_fetch_add(h + min(v, Mtop), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    };
+    if (p.flat) {
+        constexpr int G = 16 / (int)sizeof(Pin);
+        constexpr int PPW = 4 / (int)sizeof(Pin);
+        constexpr uint32_t MASK = sizeof(Pin) == 1 ? 0xFFu : 0xFFFFu;
+        const int64_t N = p.H * p.W;
+        const int64_t ngroups = N / G;
+        const KOHLER_SEG_GLOBAL seg_u32x4 *src = (const KOHLER_SEG_GLOBAL seg_u32x4 *)p.img;
+        const int64_t span = (int64_t)gridDim.x * kSegBlock * kSegUnroll;
+        for (int64_t g0 = (int64_t)blockIdx.x * kSegBlock * kSegUnroll + threadIdx.x; g0 < ngroups; g0 += span) {
+            seg_u32x4 in[kSegUnroll];
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; ++u) in[u] = src[min(g0 + (int64_t)u * kSegBlock, ngroups - 1)];
+#pragma unroll
+            for (int u = 0; u < kSegUnroll; ++u) {
+                if (g0 + (int64_t)u * kSegBlock < ngroups) {
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+#pragma unroll
+                        for (int k = 0; k < PPW; ++k) count((in[u][w] >> (8 * (int)sizeof(Pin) * k)) & MASK);
+                }
+            }
+        }
+        const KOHLER_SEG_GLOBAL Pin *s1 = (const KOHLER_SEG_GLOBAL Pin *)p.img;
+        for (int64_t i = ngroups * G + (int64_t)blockIdx.x * kSegBlock + threadIdx.x; i < N;
+             i += (int64_t)gridDim.x * kSegBlock)
+            count((uint32_t)s1[i]);
+    } else {
+        const KOHLER_SEG_GLOBAL Pin *src = (const KOHLER_SEG_GLOBAL Pin *)p.img;
+        for (int64_t r = blockIdx.x; r < p.H; r += gridDim.x)
+            for (int64_t c = threadIdx.x; c < p.W; c += kSegBlock) count((uint32_t)src[r * p.pitch + c]);
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
+        const uint32_t c = h[v];
+        if (c) __hip_atomic_fetch_add(hist + v, (unsigned long long)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+constexpr int kOneBlock = 1024;
+
+// Per-class count, value sum and mean from the histogram (level M holds the values >= M, counted
+// at the value M), for class j = levels v with #{i : t_i < v} = j. One workgroup; the class
+// accumulators live in LDS (cap + 1 pairs of 64-bit words). Clears the histogram it read.
+__global__ void __launch_bounds__(kOneBlock) class_stats_kernel(SegParams p, unsigned long long *hist,
+                                                                 int64_t *count, int64_t *sum, double *mean) {
+    extern __shared__ __align__(16) uint8_t seg_lds[];
+    KOHLER_SEG_LDS unsigned long long *ck = (KOHLER_SEG_LDS unsigned long long *)seg_lds;  // cap + 1
+    KOHLER_SEG_LDS unsigned long long *cs = ck + (p.cap + 1);                                // cap + 1
+    KOHLER_SEG_LDS int32_t *thr = (KOHLER_SEG_LDS int32_t *)(cs + (p.cap + 1));              // cap
+    const int n = min(max(*p.n_thr, 0), p.cap);
+    for (int j = threadIdx.x; j <= p.cap; j += blockDim.x) ck[j] = cs[j] = 0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) thr[i] = p.thr[i];
+    __syncthreads();
+    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
+        const unsigned long long c = hist[v];
+        if (c) {
+            const int j = rank_below(thr, n, v);
+            __hip_atomic_fetch_add(ck + j, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(cs + j, c * (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            hist[v] = 0ull;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j <= p.cap; j += blockDim.x) {
+        const int64_t c = j <= n ? (int64_t)ck[j] : 0, s = j <= n ? (int64_t)cs[j] : 0;
+        count[j] = c;
+        sum[j] = s;
+        mean[j] = c ? (double)s / (double)c : 0.0;  // one correctly rounded division
+    }
+}
+
+// sign(C(u) - C(v)) exactly for C = s / k (0 when k == 0), s, k >= 0: 128-bit cross products.
+__device__ __forceinline__ int cmp_ratio(int64_t su, int64_t ku, int64_t sv, int64_t kv) {
+    const uint64_t nu = ku ? (uint64_t)su : 0, du = ku ? (uint64_t)ku : 1;
+    const uint64_t nv = kv ? (uint64_t)sv : 0, dv = kv ? (uint64_t)kv : 1;
+    const uint64_t lh = __umul64hi(nu, dv), ll = nu * dv;
+    const uint64_t rh = __umul64hi(nv, du), rl = nv * du;
+    if (lh != rh) return lh > rh ? 1 : -1;
+    if (ll != rl) return ll > rl ? 1 : -1;
+    return 0;
+}
+
+struct TopParams {
+    const int64_t *sum, *count;
+    const int32_t *thr, *n_thr;
+    int32_t *top, *n_top;
+    int32_t M, cap, k, pad;
+};
+
+// The k thresholds of largest C, largest first, equal C in ascending t. Every threshold's place in
+// that order is its exact rank (the number of thresholds before it), so the ranks below k are the
+// output slots. Thresholds outside [0, M) count as C = 0. One workgroup.
+__global__ void __launch_bounds__(kOneBlock) top_kernel(TopParams p) {
+    const int n = min(max(*p.n_thr, 0), p.cap);
+    const int kk = min(p.k, n);
+    auto load = [&](int i, int32_t &t, int64_t &s, int64_t &c) {
+        t = p.thr[i];
+        const bool ok = t >= 0 && t < p.M;
+        s = ok ? p.sum[t] : 0;
+        c = ok ? p.count[t] : 0;
+    };
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        int32_t ti;
+        int64_t si, ci;
+        load(i, ti, si, ci);
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            int32_t tj;
+            int64_t sj, cj;
+            load(j, tj, sj, cj);
+            const int r = cmp_ratio(sj, cj, si, ci);
+            rank += (r > 0 || (r == 0 && tj < ti)) ? 1 : 0;
+        }
+        if (rank < kk) p.top[rank] = ti;
+    }
+    if (threadIdx.x == 0) *p.n_top = kk;
 }
 
 const void *seg_kernel_for(int dtype, int label_dtype) {
@@ -150,42 +300,127 @@ const void *seg_kernel_for(int dtype, int label_dtype) {
 
 using namespace kohler;
 
-extern "C" int kohler_segment(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
-                              int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
-                              void *d_labels, int label_dtype, int64_t label_pitch, kohler_stream_t stream) {
-    if (!ctx || !d_img || !d_n_thr || !d_labels) return KOHLER_E_ARG;
-    if (!valid_shape(dtype, H, W, pitch, M, 4)) return KOHLER_E_ARG;
-    if (label_dtype != KOHLER_U8 && label_dtype != KOHLER_U16) return KOHLER_E_ARG;
-    if (label_pitch < W || thr_capacity < 0 || thr_capacity > M || (thr_capacity > 0 && !d_thr)) return KOHLER_E_ARG;
-    if (label_dtype == KOHLER_U8 && thr_capacity > 255) return KOHLER_E_ARG;  // labels up to the capacity
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess) return pick_status(e);
+namespace {
 
+int64_t stream_grid(kohler_ctx *ctx, const SegParams &p, int dtype) {
+    // enough workgroups to keep every compute unit streaming, no more than the work needs
+    const int64_t esz = dtype == KOHLER_U8 ? 1 : 2;
+    const int64_t per_block = (int64_t)kSegBlock * kSegUnroll * (16 / esz);
+    const int64_t want = p.flat ? (p.H * p.W + per_block - 1) / per_block : p.H;
+    return std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * 8));
+}
+
+int launch(const void *kern, int grid, int block, void **args, size_t lds, kohler_stream_t stream) {
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipLaunchKernel(kern, dim3(grid), dim3(block), args, lds, stream);
+    if (e == hipSuccess) e = hipGetLastError();
+    return pick_status(e);
+}
+
+SegParams seg_params(const void *d_img, int64_t H, int64_t W, int64_t pitch, int32_t M, const int32_t *d_thr,
+                     const int32_t *d_n_thr, int32_t cap, void *d_out, int64_t out_pitch) {
     SegParams p{};
     p.img = d_img;
     p.H = H;
     p.W = W;
     p.pitch = pitch;
-    p.out = d_labels;
-    p.out_pitch = label_pitch;
+    p.out = d_out;
+    p.out_pitch = out_pitch;
     p.thr = d_thr;
     p.n_thr = d_n_thr;
     p.M = M;
-    p.cap = thr_capacity;
-    p.flat = (pitch == W && label_pitch == W && reinterpret_cast<uintptr_t>(d_img) % 16 == 0 &&
-              reinterpret_cast<uintptr_t>(d_labels) % 16 == 0) ? 1 : 0;
-    const size_t osz = label_dtype == KOHLER_U8 ? 1 : 2;
-    const size_t lds = (((size_t)M * osz + 15) & ~(size_t)15) + 4 * (size_t)std::max(thr_capacity, 1);
-    const void *kern = seg_kernel_for(dtype, label_dtype);
-    if ((e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-        return pick_status(e);
-    // enough workgroups to keep every compute unit streaming, no more than the work needs
-    const int64_t esz = dtype == KOHLER_U8 ? 1 : 2;
-    const int64_t per_block = (int64_t)kSegBlock * kSegUnroll * (16 / esz);
-    const int64_t want = p.flat ? (H * W + per_block - 1) / per_block : H;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * 8));
+    p.cap = cap;
+    const bool out_flat = !d_out || (out_pitch == W && reinterpret_cast<uintptr_t>(d_out) % 16 == 0);
+    p.flat = (pitch == W && reinterpret_cast<uintptr_t>(d_img) % 16 == 0 && out_flat) ? 1 : 0;
+    return p;
+}
+
+// Table (M + 1 entries of the output type) and thresholds in LDS, then the pixel stream.
+int launch_map(kohler_ctx *ctx, const SegParams &p0, int dtype, int out_dtype, kohler_stream_t stream) {
+    SegParams p = p0;
+    const size_t osz = out_dtype == KOHLER_U8 ? 1 : 2;
+    const size_t lds = (((size_t)(p.M + 1) * osz + 15) & ~(size_t)15) + 4 * (size_t)std::max(p.cap, 1);
     void *args[] = {&p};
-    e = hipLaunchKernel(kern, dim3(grid), dim3(kSegBlock), args, lds, stream);
-    if (e == hipSuccess) e = hipGetLastError();
-    return pick_status(e);
+    return launch(seg_kernel_for(dtype, out_dtype), (int)stream_grid(ctx, p, dtype), kSegBlock, args, lds, stream);
+}
+
+bool common_args(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch, int32_t M,
+                 const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity) {
+    if (!ctx || !d_img || !d_n_thr) return false;
+    if (!valid_shape(dtype, H, W, pitch, M, 4)) return false;
+    return thr_capacity >= 0 && thr_capacity <= M && (thr_capacity == 0 || d_thr);
+}
+
+}  // namespace
+
+extern "C" int kohler_segment(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                              int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
+                              void *d_labels, int label_dtype, int64_t label_pitch, kohler_stream_t stream) {
+    if (!common_args(ctx, d_img, dtype, H, W, pitch, M, d_thr, d_n_thr, thr_capacity) || !d_labels) return KOHLER_E_ARG;
+    if (label_dtype != KOHLER_U8 && label_dtype != KOHLER_U16) return KOHLER_E_ARG;
+    if (label_pitch < W) return KOHLER_E_ARG;
+    if (label_dtype == KOHLER_U8 && thr_capacity > 255) return KOHLER_E_ARG;  // labels up to the capacity
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return pick_status(e);
+    const SegParams p = seg_params(d_img, H, W, pitch, M, d_thr, d_n_thr, thr_capacity, d_labels, label_pitch);
+    return launch_map(ctx, p, dtype, label_dtype, stream);
+}
+
+extern "C" int kohler_mean_image(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                                 int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
+                                 const double *d_mean, void *d_out, int64_t out_pitch, kohler_stream_t stream) {
+    if (!common_args(ctx, d_img, dtype, H, W, pitch, M, d_thr, d_n_thr, thr_capacity) || !d_mean || !d_out)
+        return KOHLER_E_ARG;
+    if (out_pitch < W) return KOHLER_E_ARG;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return pick_status(e);
+    SegParams p = seg_params(d_img, H, W, pitch, M, d_thr, d_n_thr, thr_capacity, d_out, out_pitch);
+    p.mean = d_mean;
+    return launch_map(ctx, p, dtype, dtype, stream);  // the output has the image's type
+}
+
+extern "C" int kohler_class_stats(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                                  int32_t M, const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity,
+                                  int64_t *d_count, int64_t *d_sum, double *d_mean, kohler_stream_t stream) {
+    if (!common_args(ctx, d_img, dtype, H, W, pitch, M, d_thr, d_n_thr, thr_capacity)) return KOHLER_E_ARG;
+    if (!d_count || !d_sum || !d_mean || thr_capacity > KOHLER_MAX_CLASS_THRESHOLDS) return KOHLER_E_ARG;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return pick_status(e);
+    unsigned long long *hist = nullptr;
+    {
+        // the histogram scratch: M + 1 words for the largest M, zero between calls
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        if (!ctx->level_hist) {
+            void *q = nullptr;
+            const size_t bytes = sizeof(unsigned long long) * ((size_t)kMaxM + 1);
+            if ((e = hipMalloc(&q, bytes)) != hipSuccess) return pick_status(e);
+            if ((e = hipMemset(q, 0, bytes)) != hipSuccess) {
+                (void)hipFree(q);
+                return pick_status(e);
+            }
+            ctx->level_hist = static_cast<unsigned long long *>(q);
+        }
+        hist = ctx->level_hist;
+    }
+    SegParams p = seg_params(d_img, H, W, pitch, M, d_thr, d_n_thr, thr_capacity, nullptr, 0);
+    void *args[] = {&p, &hist};
+    const void *hk = dtype == KOHLER_U8 ? reinterpret_cast<const void *>(level_hist_kernel<uint8_t>)
+                                        : reinterpret_cast<const void *>(level_hist_kernel<uint16_t>);
+    int st = launch(hk, (int)stream_grid(ctx, p, dtype), kSegBlock, args, 4 * ((size_t)M + 1), stream);
+    if (st != KOHLER_OK) return st;
+    void *args2[] = {&p, &hist, &d_count, &d_sum, &d_mean};
+    const size_t lds = 16 * ((size_t)thr_capacity + 1) + 4 * (size_t)std::max(thr_capacity, 1);
+    return launch(reinterpret_cast<const void *>(class_stats_kernel), 1, kOneBlock, args2, lds, stream);
+}
+
+extern "C" int kohler_top_thresholds(kohler_ctx *ctx, const int64_t *d_sum, const int64_t *d_count, int32_t M,
+                                     const int32_t *d_thr, const int32_t *d_n_thr, int32_t thr_capacity, int32_t k,
+                                     int32_t *d_top, int32_t *d_n_top, kohler_stream_t stream) {
+    if (!ctx || !d_sum || !d_count || !d_n_thr || !d_n_top || M < 1 || k < 0) return KOHLER_E_ARG;
+    if (thr_capacity < 0 || thr_capacity > M || (thr_capacity > 0 && !d_thr) || (k > 0 && !d_top)) return KOHLER_E_ARG;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return pick_status(e);
+    TopParams p{d_sum, d_count, d_thr, d_n_thr, d_top, d_n_top, M, thr_capacity, k, 0};
+    void *args[] = {&p};
+    return launch(reinterpret_cast<const void *>(top_kernel), 1, kOneBlock, args, 0, stream);
 }

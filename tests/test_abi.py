@@ -88,6 +88,17 @@ def test_serving_and_tuning_argument_checks_without_device(lib):
                                ctypes.byref(us)) == _lib.E_ARG
 
 
+def test_segmentation_consumers_reject_null_context(lib):
+    from paper_1707_05062_amd import _lib
+    v = ctypes.c_void_p(16)
+    assert lib.kohler_segment(None, v, 1, 4, 4, 4, 256, v, v, 4, v, 1, 4, None) == _lib.E_ARG
+    assert lib.kohler_class_stats(None, v, 1, 4, 4, 4, 256, v, v, 4, v, v, v, None) == _lib.E_ARG
+    assert lib.kohler_mean_image(None, v, 1, 4, 4, 4, 256, v, v, 4, v, v, 4, None) == _lib.E_ARG
+    assert lib.kohler_top_thresholds(None, v, v, 256, v, v, 4, 2, v, v, None) == _lib.E_ARG
+    text = open(HEADER).read()
+    assert re.search(r"#define KOHLER_MAX_CLASS_THRESHOLDS (\d+)", text)
+
+
 def _c_struct_fields(name):
     """(type, field) pairs of a typedef struct in the header, in order."""
     text = open(HEADER).read()
