@@ -43,8 +43,8 @@ struct SegParams {
     const int32_t *thr;
     const int32_t *n_thr;
     int32_t M, cap;
-    int32_t flat;  // 1: input and output rows are contiguous (pitch == W) and 16-byte aligned
-    int32_t pad;
+    int32_t flat;    // 1: input and output rows are contiguous (pitch == W) and 16-byte aligned
+    int32_t copies;  // histogram: LDS copies of each counter (a power of two), lane l uses copy l mod copies
     const double *mean;  // non-null: the table holds each class's rounded mean instead of its label
 };
 
@@ -158,16 +158,21 @@ __global__ void __launch_bounds__(kSegBlock) segment_kernel(SegParams p) {
 
 // Grey-level histogram of the image into hist[0..M] (entry M counts every value >= M), added to
 // what hist holds. Per workgroup: LDS counters (32 bits: a workgroup sees fewer than 2^32 pixels),
-// then one device-scope atomic per non-empty level.
+// `copies` of each level side by side so that lanes of one wave counting the same grey level (flat
+// regions) mostly hit different words, then one device-scope atomic per non-empty level.
+constexpr int kHistBlock = 1024;
+
 template <typename Pin>
-__global__ void __launch_bounds__(kSegBlock) level_hist_kernel(SegParams p, unsigned long long *hist) {
+__global__ void __launch_bounds__(kHistBlock) level_hist_kernel(SegParams p, unsigned long long *hist) {
     extern __shared__ __align__(16) uint8_t seg_lds[];
-    KOHLER_SEG_LDS uint32_t *h = (KOHLER_SEG_LDS uint32_t *)seg_lds;  // M + 1 counters
-    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) h[v] = 0u;
+    KOHLER_SEG_LDS uint32_t *h = (KOHLER_SEG_LDS uint32_t *)seg_lds;  // (M + 1) * copies counters
+    const uint32_t nc = (uint32_t)p.copies;
+    for (uint32_t x = threadIdx.x; x < ((uint32_t)p.M + 1u) * nc; x += blockDim.x) h[x] = 0u;
     __syncthreads();
     const uint32_t Mtop = (uint32_t)p.M;
+    KOHLER_SEG_LDS uint32_t *hl = h + (threadIdx.x & (nc - 1u));
     auto count = [&](uint32_t v) {
-        __hip_atomic_fetch_add(h + min(v, Mtop), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(hl + min(v, Mtop) * nc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     };
     if (p.flat) {
         constexpr int G = 16 / (int)sizeof(Pin);
@@ -176,14 +181,14 @@ __global__ void __launch_bounds__(kSegBlock) level_hist_kernel(SegParams p, unsi
         const int64_t N = p.H * p.W;
         const int64_t ngroups = N / G;
         const KOHLER_SEG_GLOBAL seg_u32x4 *src = (const KOHLER_SEG_GLOBAL seg_u32x4 *)p.img;
-        const int64_t span = (int64_t)gridDim.x * kSegBlock * kSegUnroll;
-        for (int64_t g0 = (int64_t)blockIdx.x * kSegBlock * kSegUnroll + threadIdx.x; g0 < ngroups; g0 += span) {
+        const int64_t span = (int64_t)gridDim.x * kHistBlock * kSegUnroll;
+        for (int64_t g0 = (int64_t)blockIdx.x * kHistBlock * kSegUnroll + threadIdx.x; g0 < ngroups; g0 += span) {
             seg_u32x4 in[kSegUnroll];
 #pragma unroll
-            for (int u = 0; u < kSegUnroll; ++u) in[u] = src[min(g0 + (int64_t)u * kSegBlock, ngroups - 1)];
+            for (int u = 0; u < kSegUnroll; ++u) in[u] = src[min(g0 + (int64_t)u * kHistBlock, ngroups - 1)];
 #pragma unroll
             for (int u = 0; u < kSegUnroll; ++u) {
-                if (g0 + (int64_t)u * kSegBlock < ngroups) {
+                if (g0 + (int64_t)u * kHistBlock < ngroups) {
 #pragma unroll
                     for (int w = 0; w < 4; ++w)
 #pragma unroll
@@ -192,22 +197,24 @@ __global__ void __launch_bounds__(kSegBlock) level_hist_kernel(SegParams p, unsi
             }
         }
         const KOHLER_SEG_GLOBAL Pin *s1 = (const KOHLER_SEG_GLOBAL Pin *)p.img;
-        for (int64_t i = ngroups * G + (int64_t)blockIdx.x * kSegBlock + threadIdx.x; i < N;
-             i += (int64_t)gridDim.x * kSegBlock)
+        for (int64_t i = ngroups * G + (int64_t)blockIdx.x * kHistBlock + threadIdx.x; i < N;
+             i += (int64_t)gridDim.x * kHistBlock)
             count((uint32_t)s1[i]);
     } else {
         const KOHLER_SEG_GLOBAL Pin *src = (const KOHLER_SEG_GLOBAL Pin *)p.img;
         for (int64_t r = blockIdx.x; r < p.H; r += gridDim.x)
-            for (int64_t c = threadIdx.x; c < p.W; c += kSegBlock) count((uint32_t)src[r * p.pitch + c]);
+            for (int64_t c = threadIdx.x; c < p.W; c += kHistBlock) count((uint32_t)src[r * p.pitch + c]);
     }
     __syncthreads();
     for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
-        const uint32_t c = h[v];
-        if (c) __hip_atomic_fetch_add(hist + v, (unsigned long long)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long c = 0;
+        for (uint32_t k = 0; k < nc; ++k) c += h[(uint32_t)v * nc + k];
+        if (c) __hip_atomic_fetch_add(hist + v, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 constexpr int kOneBlock = 1024;
+constexpr int kHistCopies = 8;
 
 // Per-class count, value sum and mean from the histogram (level M holds the values >= M, counted
 // at the value M), for class j = levels v with #{i : t_i < v} = j. One workgroup; the class
@@ -403,10 +410,18 @@ extern "C" int kohler_class_stats(kohler_ctx *ctx, const void *d_img, int dtype,
         hist = ctx->level_hist;
     }
     SegParams p = seg_params(d_img, H, W, pitch, M, d_thr, d_n_thr, thr_capacity, nullptr, 0);
+    // as many counter copies as fit in 32 KiB of LDS (at most kHistCopies), and two 1024-thread
+    // workgroups per compute unit: each streams a large share, and few partial histograms meet in
+    // the atomics
+    p.copies = 1;
+    while (p.copies < kHistCopies && 4 * ((size_t)M + 1) * (size_t)(2 * p.copies) <= 32768) p.copies *= 2;
     void *args[] = {&p, &hist};
     const void *hk = dtype == KOHLER_U8 ? reinterpret_cast<const void *>(level_hist_kernel<uint8_t>)
                                         : reinterpret_cast<const void *>(level_hist_kernel<uint16_t>);
-    int st = launch(hk, (int)stream_grid(ctx, p, dtype), kSegBlock, args, 4 * ((size_t)M + 1), stream);
+    const int64_t per_block = (int64_t)kHistBlock * kSegUnroll * (dtype == KOHLER_U8 ? 16 : 8);
+    const int64_t want = p.flat ? (H * W + per_block - 1) / per_block : H;
+    const int hgrid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * 2));
+    int st = launch(hk, hgrid, kHistBlock, args, 4 * ((size_t)M + 1) * (size_t)p.copies, stream);
     if (st != KOHLER_OK) return st;
     void *args2[] = {&p, &hist, &d_count, &d_sum, &d_mean};
     const size_t lds = 16 * ((size_t)thr_capacity + 1) + 4 * (size_t)std::max(thr_capacity, 1);
