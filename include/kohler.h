@@ -203,9 +203,10 @@ int kohler_segment(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int
  *   d_count, d_sum   int64[thr_capacity + 1]: pixels and sum of their values per class
  *   d_mean           double[thr_capacity + 1]: sum / count, one correctly rounded division, 0.0 for
  *                    an empty class
- * Entries past the n + 1 classes in use are 0. Two kernel launches: a grey-level histogram (each
- * pixel read once) into a context scratch array, then one workgroup that folds it into the classes
- * and clears it; calls on one context must not overlap on the device (they share that array).
+ * Entries past the n + 1 classes in use are 0. One kernel launch: a grey-level histogram (each
+ * pixel read once) into a context scratch array, which the workgroup that finishes last folds into
+ * the classes and clears; calls on one context must not overlap on the device (they share that
+ * array).
  * Allocates the scratch on the first call. Returns KOHLER_OK, KOHLER_E_ARG, KOHLER_E_NOMEM or
  * KOHLER_E_DEVICE.
  */

@@ -9,10 +9,10 @@
 //                      search per level over the thresholds in LDS; level M stands for every value
 //                      >= M), then maps pixels through it, 16 bytes of input per lane and step, with
 //                      loads of several steps in flight. Each pixel is read once and written once.
-//   level_hist_kernel  the image's grey-level histogram (same stream shape, LDS counters per
-//                      workgroup, one global atomic per non-empty level and workgroup)
-//   class_stats_kernel one workgroup: folds the histogram into per-class count, sum and mean, and
-//                      clears the histogram for the next call
+//   class_stats_kernel the image's grey-level histogram (same stream shape, LDS counters per
+//                      workgroup, one global atomic per non-empty level and workgroup), folded
+//                      into per-class count, sum and mean by the workgroup that finishes last,
+//                      which also clears the histogram for the next call
 //   top_kernel         one workgroup: the k thresholds of largest C, by exact rank
 //
 // The entry points (kohler_segment, kohler_class_stats, kohler_mean_image, kohler_top_thresholds) are
@@ -156,14 +156,56 @@ __global__ void __launch_bounds__(kSegBlock) segment_kernel(SegParams p) {
     }
 }
 
-// Grey-level histogram of the image into hist[0..M] (entry M counts every value >= M), added to
-// what hist holds. Per workgroup: LDS counters (32 bits: a workgroup sees fewer than 2^32 pixels),
-// `copies` of each level side by side so that lanes of one wave counting the same grey level (flat
-// regions) mostly hit different words, then one device-scope atomic per non-empty level.
+// Memory shared between the workgroups of the class-statistics launch (histogram, ticket) is only
+// touched with system-scope atomics, which are performed past the per-XCD L2 caches: a workgroup's
+// additions are complete once their returned values have arrived, so the workgroup that takes the
+// last ticket sees every addition without a device-wide cache flush.
+#define KOHLER_SEG_XSCOPE __HIP_MEMORY_SCOPE_SYSTEM
+
 constexpr int kHistBlock = 1024;
 
+// Per-class count, value sum and mean for class j = levels v with #{i : t_i < v} = j, from the
+// histogram (level M holds the values >= M, counted at the value M), by the workgroup that took the
+// last ticket; the class accumulators live in LDS (cap + 1 pairs of 64-bit words). Clears the
+// histogram and the ticket for the next call.
+__device__ void fold_classes(const SegParams &p, unsigned long long *hist, unsigned long long *ticket,
+                             int64_t *count, int64_t *sum, double *mean, KOHLER_SEG_LDS uint8_t *lds) {
+    KOHLER_SEG_LDS unsigned long long *ck = (KOHLER_SEG_LDS unsigned long long *)lds;  // cap + 1
+    KOHLER_SEG_LDS unsigned long long *cs = ck + (p.cap + 1);                           // cap + 1
+    KOHLER_SEG_LDS int32_t *thr = (KOHLER_SEG_LDS int32_t *)(cs + (p.cap + 1));         // cap
+    const int n = min(max(*p.n_thr, 0), p.cap);
+    for (int j = threadIdx.x; j <= p.cap; j += blockDim.x) ck[j] = cs[j] = 0ull;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) thr[i] = p.thr[i];
+    __syncthreads();
+    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
+        const unsigned long long c = __hip_atomic_load(hist + v, __ATOMIC_RELAXED, KOHLER_SEG_XSCOPE);
+        if (c) {
+            const int j = rank_below(thr, n, v);
+            __hip_atomic_fetch_add(ck + j, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(cs + j, c * (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_store(hist + v, 0ull, __ATOMIC_RELAXED, KOHLER_SEG_XSCOPE);
+        }
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(ticket, 0ull, __ATOMIC_RELAXED, KOHLER_SEG_XSCOPE);
+    __syncthreads();
+    for (int j = threadIdx.x; j <= p.cap; j += blockDim.x) {
+        const int64_t c = j <= n ? (int64_t)ck[j] : 0, s = j <= n ? (int64_t)cs[j] : 0;
+        count[j] = c;
+        sum[j] = s;
+        mean[j] = c ? (double)s / (double)c : 0.0;  // one correctly rounded division
+    }
+}
+
+// Class statistics in one launch. Every workgroup counts its share of the pixels into LDS counters
+// (32 bits: a workgroup sees fewer than 2^32 pixels), `copies` of each level side by side so that
+// lanes of one wave counting the same grey level (flat regions) mostly hit different words, adds
+// its non-empty levels to hist[0..M] (entry M counts every value >= M), then takes a ticket; the
+// last workgroup folds the histogram into the classes.
+
 template <typename Pin>
-__global__ void __launch_bounds__(kHistBlock) level_hist_kernel(SegParams p, unsigned long long *hist) {
+__global__ void __launch_bounds__(kHistBlock) class_stats_kernel(SegParams p, unsigned long long *hist,
+                                                                  unsigned long long *ticket, int64_t *out_count,
+                                                                  int64_t *out_sum, double *out_mean) {
     extern __shared__ __align__(16) uint8_t seg_lds[];
     KOHLER_SEG_LDS uint32_t *h = (KOHLER_SEG_LDS uint32_t *)seg_lds;  // (M + 1) * copies counters
     const uint32_t nc = (uint32_t)p.copies;
@@ -206,46 +248,29 @@ __global__ void __launch_bounds__(kHistBlock) level_hist_kernel(SegParams p, uns
             for (int64_t c = threadIdx.x; c < p.W; c += kHistBlock) count((uint32_t)src[r * p.pitch + c]);
     }
     __syncthreads();
+    uint64_t sink = 0;
     for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
         unsigned long long c = 0;
         for (uint32_t k = 0; k < nc; ++k) c += h[(uint32_t)v * nc + k];
-        if (c) __hip_atomic_fetch_add(hist + v, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (c) sink ^= __hip_atomic_fetch_add(hist + v, c, __ATOMIC_RELAXED, KOHLER_SEG_XSCOPE);
     }
+    // consuming the returned values makes the wave wait until its additions are performed
+    asm volatile("" ::"v"((uint32_t)sink), "v"((uint32_t)(sink >> 32)));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    KOHLER_SEG_LDS uint32_t *last = h;  // the counters are dead now
+    if (threadIdx.x == 0) {
+        const unsigned long long old = __hip_atomic_fetch_add(ticket, 1ull, __ATOMIC_RELAXED, KOHLER_SEG_XSCOPE);
+        *last = (old + 1ull == (unsigned long long)gridDim.x) ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool is_last = *last != 0u;
+    __syncthreads();  // every thread has read the flag before the fold reuses the LDS
+    if (is_last) fold_classes(p, hist, ticket, out_count, out_sum, out_mean, (KOHLER_SEG_LDS uint8_t *)seg_lds);
 }
 
 constexpr int kOneBlock = 1024;
 constexpr int kHistCopies = 8;
-
-// Per-class count, value sum and mean from the histogram (level M holds the values >= M, counted
-// at the value M), for class j = levels v with #{i : t_i < v} = j. One workgroup; the class
-// accumulators live in LDS (cap + 1 pairs of 64-bit words). Clears the histogram it read.
-__global__ void __launch_bounds__(kOneBlock) class_stats_kernel(SegParams p, unsigned long long *hist,
-                                                                 int64_t *count, int64_t *sum, double *mean) {
-    extern __shared__ __align__(16) uint8_t seg_lds[];
-    KOHLER_SEG_LDS unsigned long long *ck = (KOHLER_SEG_LDS unsigned long long *)seg_lds;  // cap + 1
-    KOHLER_SEG_LDS unsigned long long *cs = ck + (p.cap + 1);                                // cap + 1
-    KOHLER_SEG_LDS int32_t *thr = (KOHLER_SEG_LDS int32_t *)(cs + (p.cap + 1));              // cap
-    const int n = min(max(*p.n_thr, 0), p.cap);
-    for (int j = threadIdx.x; j <= p.cap; j += blockDim.x) ck[j] = cs[j] = 0ull;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) thr[i] = p.thr[i];
-    __syncthreads();
-    for (int v = threadIdx.x; v <= p.M; v += blockDim.x) {
-        const unsigned long long c = hist[v];
-        if (c) {
-            const int j = rank_below(thr, n, v);
-            __hip_atomic_fetch_add(ck + j, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            __hip_atomic_fetch_add(cs + j, c * (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            hist[v] = 0ull;
-        }
-    }
-    __syncthreads();
-    for (int j = threadIdx.x; j <= p.cap; j += blockDim.x) {
-        const int64_t c = j <= n ? (int64_t)ck[j] : 0, s = j <= n ? (int64_t)cs[j] : 0;
-        count[j] = c;
-        sum[j] = s;
-        mean[j] = c ? (double)s / (double)c : 0.0;  // one correctly rounded division
-    }
-}
 
 // sign(C(u) - C(v)) exactly for C = s / k (0 when k == 0), s, k >= 0: 128-bit cross products.
 __device__ __forceinline__ int cmp_ratio(int64_t su, int64_t ku, int64_t sv, int64_t kv) {
@@ -399,7 +424,7 @@ extern "C" int kohler_class_stats(kohler_ctx *ctx, const void *d_img, int dtype,
         std::lock_guard<std::mutex> lk(ctx->mu);
         if (!ctx->level_hist) {
             void *q = nullptr;
-            const size_t bytes = sizeof(unsigned long long) * ((size_t)kMaxM + 1);
+            const size_t bytes = sizeof(unsigned long long) * ((size_t)kMaxM + 2);  // histogram, ticket
             if ((e = hipMalloc(&q, bytes)) != hipSuccess) return pick_status(e);
             if ((e = hipMemset(q, 0, bytes)) != hipSuccess) {
                 (void)hipFree(q);
@@ -415,17 +440,16 @@ extern "C" int kohler_class_stats(kohler_ctx *ctx, const void *d_img, int dtype,
     // the atomics
     p.copies = 1;
     while (p.copies < kHistCopies && 4 * ((size_t)M + 1) * (size_t)(2 * p.copies) <= 32768) p.copies *= 2;
-    void *args[] = {&p, &hist};
-    const void *hk = dtype == KOHLER_U8 ? reinterpret_cast<const void *>(level_hist_kernel<uint8_t>)
-                                        : reinterpret_cast<const void *>(level_hist_kernel<uint16_t>);
+    unsigned long long *ticket = hist + (kMaxM + 1);
+    void *args[] = {&p, &hist, &ticket, &d_count, &d_sum, &d_mean};
+    const void *hk = dtype == KOHLER_U8 ? reinterpret_cast<const void *>(class_stats_kernel<uint8_t>)
+                                        : reinterpret_cast<const void *>(class_stats_kernel<uint16_t>);
     const int64_t per_block = (int64_t)kHistBlock * kSegUnroll * (dtype == KOHLER_U8 ? 16 : 8);
     const int64_t want = p.flat ? (H * W + per_block - 1) / per_block : H;
     const int hgrid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * 2));
-    int st = launch(hk, hgrid, kHistBlock, args, 4 * ((size_t)M + 1) * (size_t)p.copies, stream);
-    if (st != KOHLER_OK) return st;
-    void *args2[] = {&p, &hist, &d_count, &d_sum, &d_mean};
-    const size_t lds = 16 * ((size_t)thr_capacity + 1) + 4 * (size_t)std::max(thr_capacity, 1);
-    return launch(reinterpret_cast<const void *>(class_stats_kernel), 1, kOneBlock, args2, lds, stream);
+    const size_t lds = std::max(4 * ((size_t)M + 1) * (size_t)p.copies,
+                                16 * ((size_t)thr_capacity + 1) + 4 * (size_t)std::max(thr_capacity, 1));
+    return launch(hk, hgrid, kHistBlock, args, lds, stream);
 }
 
 extern "C" int kohler_top_thresholds(kohler_ctx *ctx, const int64_t *d_sum, const int64_t *d_count, int32_t M,
