@@ -51,3 +51,60 @@ def test_mutant_is_caught(name, tmp_path):
         except (AssertionError, oracle.OracleError) as e:
             caught.append((pin.__name__, str(e)[:80]))
     assert caught, f"mutant {name} passed every pin"
+
+
+# Mistakes planted in the oracle's Python functions (segmentation and its consumers): each is a
+# textual edit of the function's source, compiled into a copy of the module's namespace and swapped
+# in for the duration of the test only.
+PY_MUTANTS = {
+    # Sec. 2.1 / eq (1): a value equal to a threshold lies in the threshold's lower set
+    "segment_nonstrict": ("segment", "(blk[..., None] > t[None, None, :])", "(blk[..., None] >= t[None, None, :])"),
+    # class mean: sum over count
+    "class_mean_transposed": ("class_stats", "mean[j] = np.float64(total[j]) / np.float64(count[j])",
+                              "mean[j] = np.float64(count[j]) / np.float64(total[j])"),
+    # values >= M count at the value M
+    "class_clamp_below_M": ("class_stats", "f = np.minimum(np.asarray(img).astype(np.int64), M)",
+                            "f = np.minimum(np.asarray(img).astype(np.int64), M - 1)"),
+    # rounding of the class means: ties to even
+    "mean_round_half_up": ("mean_image", "return np.rint(mean)[lab].astype(img.dtype)",
+                           "return np.floor(mean + 0.5)[lab].astype(img.dtype)"),
+    # most significant thresholds: exact order, equal C in ascending t
+    "top_float_order": ("top_thresholds", "return (-(Fraction(int(sum_[t]), c) if c else Fraction(0)), int(t))",
+                        "return (-(int(sum_[t]) / c if c else 0.0), int(t))"),
+    "top_tie_larger_t": ("top_thresholds", "return (-(Fraction(int(sum_[t]), c) if c else Fraction(0)), int(t))",
+                         "return (-(Fraction(int(sum_[t]), c) if c else Fraction(0)), -int(t))"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_python_mutant_is_caught(name, monkeypatch):
+    import inspect
+    import textwrap
+
+    fn, old, new = PY_MUTANTS[name]
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, fn)))
+    assert src.count(old) == 1, f"mutation anchor for {name} not found exactly once"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), ns)
+    monkeypatch.setattr(oracle, fn, ns[fn])
+    caught = []
+    for pin in (_pins.pin_segment, _pins.pin_class_stats):
+        try:
+            pin()
+        except AssertionError as e:
+            caught.append((pin.__name__, str(e)[:80]))
+    assert caught, f"mutant {name} passed every pin"
+
+
+@pytest.mark.parametrize("fn", sorted({v[0] for v in PY_MUTANTS.values()}))
+def test_python_unmutated_copy_passes(fn, monkeypatch):
+    """Control: the same recompilation without an edit passes every pin, so a caught mutant is caught
+    for its edit."""
+    import inspect
+    import textwrap
+
+    ns = dict(vars(oracle))
+    exec(compile(textwrap.dedent(inspect.getsource(getattr(oracle, fn))), f"<copy {fn}>", "exec"), ns)
+    monkeypatch.setattr(oracle, fn, ns[fn])
+    _pins.pin_segment()
+    _pins.pin_class_stats()
