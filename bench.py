@@ -104,7 +104,7 @@ def measured_traffic(plan: dict):
 
 
 def parse_plan(s: str) -> dict:
-    keys = ("form", "band", "block", "grid", "px_per_lane", "replicas")
+    keys = ("form", "band", "block", "grid", "px_per_lane", "replicas", "copies")
     vals = [int(x) for x in s.split(":")]
     return dict(zip(keys, vals))
 
@@ -527,7 +527,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--rotate", type=int, default=32, help="distinct input buffers cycled by the steps")
-    ap.add_argument("--plan", default="", help="fixed plan form:band:block:grid:px_per_lane:replicas "
+    ap.add_argument("--plan", default="", help="fixed plan form:band:block:grid:px_per_lane:replicas[:copies] "
                                                "instead of autotuning")
     ap.add_argument("--only", choices=["all", "headline", "curve"], default="all",
                     help="headline: the curve and the segmentation of the 18 MP image only; curve: the curve only")

@@ -129,13 +129,19 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
  *   form        0 = automatic, 1 = banded joint histogram (M <= 256), 2 = marginal histograms,
  *               3 = triangular joint histogram of (lo, hi) (M <= 256)
  *   band        number of gap rows of the banded table (1..64; form 1 only)
- *   block       threads per workgroup (256 or 512)
+ *   block       threads per workgroup (256, 512 or 1024)
  *   grid        workgroups per launch (0 = automatic: enough to fill every compute unit)
  *   px_per_lane pixels each lane loads per row (4 or 8 for KOHLER_U8, 4 for KOHLER_U16); a tile is
  *               one row of a strip of 64 * px_per_lane columns
  *   replicas    merge schedule: copies of the per-image device accumulators that the workgroups'
  *               partial histograms are added into (1..16; 0 = automatic, about one per 32
  *               workgroups); the finishing workgroup sums the copies
+ *   copies      LDS privatisation width of the banded form: copies of the joint table each
+ *               workgroup keeps, lane l of a wave adding to copy l % copies (1, 2 or 4; 0 =
+ *               automatic; other forms use 1)
+ * The grid is raised where needed so that no workgroup's 32-bit LDS counter can overflow: at least
+ * ceil(w * 64 * px_per_lane * units / 2^31) workgroups for a launch over `units` tile rows, with w = 2
+ * (nbhd 4) or 4 (nbhd 8) pairs per pixel, 8 for the marginal form.
  * kohler_set_plan stores a plan in the context for later calls (KOHLER_E_ARG if it is invalid);
  * kohler_get_plan reports the plan a call with these parameters would use.
  */
@@ -146,6 +152,7 @@ typedef struct kohler_plan {
     int32_t grid;
     int32_t px_per_lane;
     int32_t replicas;
+    int32_t copies;
 } kohler_plan;
 
 int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const kohler_plan *plan);
@@ -157,8 +164,8 @@ int kohler_get_plan(kohler_ctx *ctx, int dtype, int64_t H, int64_t W, int32_t M,
  * and stores the fastest in the context, as kohler_set_plan would. The workload is described as in
  * kohler_curve_batch (n device images; n == 1 tunes the single-image launch, n > 1 the batched
  * one). The search is a coordinate descent, two passes over the knobs in the order tile shape
- * (form and band), px_per_lane, block, grid (automatic or 1..4 workgroups per compute unit) and
- * replicas, starting from the default plan, then a joint sweep of band (banded form),
+ * (form and band), table copies, px_per_lane, block, grid (automatic or 1..4 workgroups per compute
+ * unit) and replicas, starting from the default plan, then a joint sweep of band (banded form),
  * px_per_lane, grid and replicas (1, 2, 4, 8) around the result; each
  * candidate gets two warm-up launches and `reps` timed ones (0 means 5) on the context's stream,
  * and its median time counts.

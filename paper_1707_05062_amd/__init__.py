@@ -87,8 +87,9 @@ def _ptr(t):
 class Context:
     """A library context bound to one HIP device (owns device scratch and a stream)."""
 
-    def __init__(self, device: int = 0):
-        self._lib = _lib.load()
+    def __init__(self, device: int = 0, lib_path: str | None = None):
+        # lib_path: another build of the same library (e.g. the phase-clock measurement build)
+        self._lib = _lib.load() if lib_path is None else _lib.load(lib_path)
         self._h = ctypes.c_void_p()
         st = self._lib.kohler_create(ctypes.byref(self._h), int(device))
         if st != OK:
@@ -108,8 +109,8 @@ class Context:
 
     # -- plans -------------------------------------------------------------------------------
     def set_plan(self, dtype: int, M: int, nbhd: int, form: int = FORM_AUTO, band: int = 0,
-                 block: int = 512, grid: int = 0, px_per_lane: int = 4, replicas: int = 0):
-        pl = Plan(form, band, block, grid, px_per_lane, replicas)
+                 block: int = 512, grid: int = 0, px_per_lane: int = 4, replicas: int = 0, copies: int = 0):
+        pl = Plan(form, band, block, grid, px_per_lane, replicas, copies)
         st = self._lib.kohler_set_plan(self._h, dtype, M, nbhd, ctypes.byref(pl))
         if st != OK:
             raise KohlerError(st, "kohler_set_plan")

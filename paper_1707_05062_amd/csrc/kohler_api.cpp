@@ -44,7 +44,9 @@ bool valid_plan(const kohler_plan &pl, int dtype, int32_t M) {
     if (pl.form == FORM_BAND && (M > kMaxMBand || pl.band < 1 || pl.band > kMaxBandRows)) return false;
     if (pl.form == FORM_TRI && M > kMaxMBand) return false;
     if (pl.form == FORM_MARG && M > kMaxMMarg) return false;
-    if (pl.block != 256 && pl.block != 512) return false;
+    if (pl.block != 256 && pl.block != 512 && pl.block != 1024) return false;
+    if (pl.copies != 1 && pl.copies != 2 && pl.copies != 4) return false;
+    if (pl.form != FORM_BAND && pl.copies != 1) return false;
     if (pl.grid < 0 || pl.grid > 65535) return false;
     if (pl.replicas < 0 || pl.replicas > kMaxReplicas) return false;
     if (dtype == KOHLER_U8 && pl.px_per_lane != 4 && pl.px_per_lane != 8) return false;
@@ -60,6 +62,7 @@ kohler_plan default_plan(int dtype, int32_t M) {
     pl.grid = 0;
     pl.px_per_lane = 4;
     pl.replicas = 0;
+    pl.copies = pl.form == FORM_BAND ? 2 : 1;
     (void)dtype;
     return pl;
 }
@@ -75,11 +78,17 @@ kohler_plan resolve_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, in
     if ((pl.form == FORM_BAND || pl.form == FORM_TRI) && M > kMaxMBand) pl = default_plan(dtype, M);
     if (pl.replicas == 0) pl.replicas = -1;  // filled in below, once the grid is known
     if (pl.grid == 0) {
-        const int per_cu = blocks_per_cu(dtype, nbhd, pl.form, pl.px_per_lane, M, pl.band, pl.block);
+        const int per_cu = blocks_per_cu(dtype, nbhd, pl.form, pl.px_per_lane, M, pl.band, pl.block, pl.copies);
         const int64_t waves = pl.block / 64;
         const int64_t want = (total_units + waves * 4 - 1) / (waves * 4);  // >= 4 rows per wave
         pl.grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * per_cu));
     }
+    // Every LDS counter of a workgroup is 32 bits: it counts at most w per pixel the workgroup sees
+    // (pairs per pixel, or the degree weight of the marginal form), and a workgroup sees about
+    // units / grid tile rows (plus one chunk), so half the counter range bounds the grid from below.
+    const int64_t w = pl.form == FORM_MARG ? 8 : (nbhd == 4 ? 2 : 4);
+    const int64_t min_grid = (w * 64 * pl.px_per_lane * total_units + (int64_t(1) << 31) - 1) >> 31;
+    if (pl.grid < min_grid) pl.grid = (int)std::min<int64_t>(min_grid, 65535);
     if (pl.replicas < 0) pl.replicas = replicas_for(pl.grid);
     return pl;
 }
@@ -136,6 +145,7 @@ int launch(kohler_ctx *ctx, const KParams &base, int dtype, int32_t nbhd, const 
            hipStream_t stream) {
     KParams p = base;
     p.band = pl.band;
+    p.copies = pl.copies;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return pick_status(e);
     e = launch_curve(p, dtype, nbhd, pl.form, pl.px_per_lane, pl.block, pl.grid, stream);
@@ -231,8 +241,10 @@ int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const k
         if (pl.band == 0) pl.band = d.band;
     }
     if ((pl.form == FORM_MARG || pl.form == FORM_TRI) && pl.band == 0) pl.band = 1;
+    if (pl.copies == 0) pl.copies = pl.form == FORM_BAND ? 2 : 1;
     if (!valid_plan(pl, dtype, M)) return KOHLER_E_ARG;
-    if (lds_bytes(pl.form, M, pl.band, pl.block) > kMaxLdsBytes) return KOHLER_E_ARG;
+    if (lds_bytes(pl.form, M, pl.band, pl.block, pl.copies) > kMaxLdsBytes) return KOHLER_E_ARG;
+    if (pl.block > max_block_for(dtype, nbhd, pl.form, pl.px_per_lane, M)) return KOHLER_E_ARG;
     std::lock_guard<std::mutex> lk(ctx->mu);
     ctx->plans[std::make_tuple(dtype, (int)M, (int)nbhd)] = pl;
     return KOHLER_OK;
@@ -489,9 +501,9 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
                                   cap, d_n, d_t0, d_st, ctx->stream);
     };
     // median launch time of a plan in microseconds, or a negative status
-    std::map<std::tuple<int, int, int, int, int, int>, double> seen;
+    std::map<std::tuple<int, int, int, int, int, int, int>, double> seen;
     auto time_plan = [&](const kohler_plan &pl, double *us) -> int {
-        const auto k = std::make_tuple(pl.form, pl.band, pl.block, pl.grid, pl.px_per_lane, pl.replicas);
+        const auto k = std::make_tuple(pl.form, pl.band, pl.block, pl.grid, pl.px_per_lane, pl.replicas, pl.copies);
         auto it = seen.find(k);
         if (it != seen.end()) {
             *us = it->second;
@@ -524,7 +536,7 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
     if (M <= kMaxMBand) shapes.emplace_back(FORM_TRI, 1);
     if (M <= kMaxMMarg) shapes.emplace_back(FORM_MARG, 1);
     std::vector<int> ppls = dtype == KOHLER_U8 ? std::vector<int>{4, 8} : std::vector<int>{4};
-    const std::vector<int> blocks = {256, 512};
+    const std::vector<int> blocks = {256, 512, 1024};
     const std::vector<int> reps_knob = {0, 1, 2, 4, 8, 16};
 
     kohler_plan cur = default_plan(dtype, M);
@@ -550,7 +562,17 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
             kohler_plan pl = base_shape;
             pl.form = fb.first;
             pl.band = fb.second;
+            if (pl.form != FORM_BAND) pl.copies = 1;
+            else if (base_shape.form != FORM_BAND) pl.copies = 2;
             try_plan(pl);
+        }
+        if (cur.form == FORM_BAND) {
+            const kohler_plan base_copies = cur;
+            for (int v : {1, 2, 4}) {
+                kohler_plan pl = base_copies;
+                pl.copies = v;
+                try_plan(pl);
+            }
         }
         const kohler_plan base_ppl = cur;
         for (int v : ppls) {
@@ -566,7 +588,7 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
         }
         // grid: automatic, or 1..4 workgroups per compute unit within the occupancy limit
         const kohler_plan base_grid = cur;
-        const int per_cu = blocks_per_cu(dtype, nbhd, cur.form, cur.px_per_lane, M, cur.band, cur.block);
+        const int per_cu = blocks_per_cu(dtype, nbhd, cur.form, cur.px_per_lane, M, cur.band, cur.block, cur.copies);
         for (int v = 0; v <= std::min(4, per_cu); ++v) {
             kohler_plan pl = base_grid;
             pl.grid = v * ctx->num_cus;
@@ -589,7 +611,7 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
                 if (b != base.band && b <= std::max(1, M - 1)) bands.push_back(b);
         for (int bv : bands)
             for (int pv : ppls) {
-                const int per_cu = blocks_per_cu(dtype, nbhd, base.form, pv, M, bv, base.block);
+                const int per_cu = blocks_per_cu(dtype, nbhd, base.form, pv, M, bv, base.block, base.copies);
                 for (int gv = 0; gv <= std::min(4, per_cu); ++gv)
                     for (int rv : {1, 2, 4, 8}) {
                         if (st != KOHLER_OK) break;

@@ -41,7 +41,7 @@ struct KParams {
                           // contrast sums (or both packed in the first M words); zero between launches
     unsigned long long *done;  // per output index: units completed in the current launch; zero between launches
     int32_t dyn;          // 1: one image, chunks dealt round-robin to the workgroups
-    int32_t pad1;
+    int32_t copies;       // banded form: copies of the joint table per workgroup (lane l uses copy l % copies)
     uint32_t *rflag;      // per output index: set when a pixel >= M was seen; zero between launches
     int64_t ostride;      // elements between the sum/count/C arrays of two output indices
     int64_t istride;      // elements between the n_thr/t0/status entries of two output indices
@@ -80,39 +80,53 @@ struct BlockScratch {
     int32_t pad[2];
 };
 
-// The banded table's rows are 257 words apart, so that the LDS bank of a counter depends on both
-// the gap and the low value (a 256-word stride would put every gap of one low value in one bank).
-constexpr int kRowStride = 257;
+// Words between two rows of the banded table (at least 257: a row holds 256 low values, and the
+// word after them must stay zero, see merge_band). The stride sets which LDS bank a counter (d, lo)
+// falls in, (d * stride + lo) mod banks: with 257 the bank is hi mod banks, which neighbouring pixels
+// of a smooth image share; a stride of 256 + 16 spreads the gaps over the banks as well.
+#ifndef KOHLER_ROW_STRIDE
+#define KOHLER_ROW_STRIDE 272
+#endif
+constexpr int kRowStride = KOHLER_ROW_STRIDE;
+static_assert(kRowStride >= 257, "a row of the banded table needs 256 counters and one zero word");
+
+// Copies of the banded table a workgroup may keep (lanes spread over them, so fewer lanes of one
+// LDS instruction add to the same counter).
+constexpr int kMaxBandCopies = 4;
 
 // LDS bytes before the BlockScratch: the histogram tables, or the finalize step's arrays, whichever
-// is larger; 16-byte aligned. Finalize for M <= 256 keeps two int64 partial sums per wave and level
-// (256 levels); for larger M, two int64 arrays of block + 1 entries and one byte per grey level.
-__host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int block) {
-    // triangular form: M (M + 1) / 2 counters, 64 invalid-pair words, then hmin, hmax (M each) and
-    // hsum (2M, one spare)
-    const size_t words = (form == FORM_BAND)  ? ((size_t)band + 2) * kRowStride + 768
+// is larger; 16-byte aligned. Finalize for M <= 256 needs 8 KiB (the curve and per-wave masks); for
+// larger M, two int64 arrays of block + 1 entries and one byte per grey level.
+__host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int block, int copies) {
+    // banded form: `copies` tables of band + 2 rows, then the hmax and hsum tables of the gaps beyond
+    // the band (768 words); triangular form: M (M + 1) / 2 counters, 64 invalid-pair words, then
+    // hmin, hmax (M each) and hsum (2M, one spare)
+    const size_t words = (form == FORM_BAND)  ? (size_t)copies * ((size_t)band + 2) * kRowStride + 768
                          : (form == FORM_TRI) ? (size_t)M * (M + 1) / 2 + 64 + 4 * (size_t)M
                                               : 4 * (size_t)M;
     const size_t table = (words * 4 + 15) & ~(size_t)15;
-    const size_t fin = M <= 256 ? (size_t)(block / 64) * 2 * 256 * 8
+    const size_t fin = M <= 256 ? (size_t)8192
                                 : (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
     return table > fin ? table : fin;
 }
 
-// LDS bytes a launch needs for (form, M, band, threads per workgroup).
-inline size_t lds_bytes(int form, int M, int band, int block) {
-    return lds_main_bytes(form, M, band, block) + sizeof(BlockScratch);
+// LDS bytes a launch needs for (form, M, band, threads per workgroup, table copies).
+inline size_t lds_bytes(int form, int M, int band, int block, int copies) {
+    return lds_main_bytes(form, M, band, block, copies) + sizeof(BlockScratch);
 }
 
+// Largest workgroup (threads) the kernel instance of a launch family was compiled for (0 on error).
+int max_block_for(int dtype, int nbhd, int form, int px_per_lane, int M);
+
 // Workgroups of this launch family that fit on one compute unit at once.
-int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block);
+int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block, int copies);
 
 // The kernel instance of a launch family and the dynamic LDS bytes it needs (for graph kernel
 // nodes); allows the kernel to use that much LDS.
 hipError_t curve_kernel_for(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block,
-                            const void **func, size_t *lds);
+                            int copies, const void **func, size_t *lds);
 
-// Launch the curve kernel. Returns hipSuccess or the launch error.
+// Launch the curve kernel (p.band and p.copies already set). Returns hipSuccess or the launch error.
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,
                         int grid, hipStream_t stream);
 

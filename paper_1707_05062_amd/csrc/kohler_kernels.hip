@@ -39,10 +39,7 @@
 namespace kohler {
 namespace {
 
-constexpr int kRowBatch = 4;  // rows whose loads a wave issues together before using them
-constexpr int kChunk = 4;     // units (rows of a strip) a wave claims at a time
-constexpr int kTailRows = 2;  // rows of the pieces a workgroup's last chunks are claimed in
-static_assert(kChunk % kTailRows == 0, "a chunk splits into whole pieces");
+constexpr int kChunk = 4;     // units (rows of a strip) a wave claims at a time in a batched launch
 
 // Explicit address spaces keep loads, stores and atomics on the global (not flat) and LDS paths.
 #define KOHLER_GLOBAL __attribute__((address_space(1)))
@@ -63,6 +60,43 @@ __device__ __forceinline__ KOHLER_GLOBAL T *gptr(T *p) {
 
 enum : int32_t { ST_OK = 0, ST_RANGE = -2, ST_CAPACITY = -3, ST_LAYOUT = -5 };
 
+// Measurement build only (-DKOHLER_PHASE_CLOCK): each workgroup of the curve kernel records the
+// constant 100 MHz real-time counter at its phase boundaries, and each wave the end of its pair
+// work, in device arrays that kohler_phase_clock_read copies out. Slots per workgroup:
+//   0 entry, 1 tables cleared, 2 every wave's pairs done, 3 projection on the marginals done,
+//   4 merge atomics performed, 5 ticket taken, 6 finishing workgroup: replicas gathered,
+//   7 finishing workgroup: done, 8 the hardware id register of the workgroup's first wave (compute
+//   unit, shader array, engine), 9 the id of its accelerator complex die (XCD), 10 and 11 the
+//   shader clock (cycles) at stamps 6 and 7.
+#ifdef KOHLER_PHASE_CLOCK
+constexpr int kPhaseSlots = 12;
+constexpr int kPhaseMaxWG = 4096;
+constexpr int kPhaseWaves = 16;
+__device__ unsigned long long g_phase[kPhaseMaxWG * kPhaseSlots];
+__device__ unsigned long long g_phase_wave[kPhaseMaxWG * kPhaseWaves];
+__device__ __forceinline__ void phase_stamp(int slot) {
+    if (threadIdx.x == 0 && blockIdx.x < (unsigned)kPhaseMaxWG) {
+        gptr(g_phase)[blockIdx.x * kPhaseSlots + slot] = (unsigned long long)wall_clock64();
+        if (slot == 6 || slot == 7) gptr(g_phase)[blockIdx.x * kPhaseSlots + slot + 4] = (unsigned long long)clock64();
+    }
+}
+__device__ __forceinline__ void phase_place() {
+    if (threadIdx.x == 0 && blockIdx.x < (unsigned)kPhaseMaxWG) {
+        gptr(g_phase)[blockIdx.x * kPhaseSlots + 8] = __builtin_amdgcn_s_getreg(4 | (31 << 11));
+        gptr(g_phase)[blockIdx.x * kPhaseSlots + 9] = __builtin_amdgcn_s_getreg(20 | (15 << 11));
+    }
+}
+__device__ __forceinline__ void phase_wave_stamp() {
+    const unsigned w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0 && blockIdx.x < (unsigned)kPhaseMaxWG && w < (unsigned)kPhaseWaves)
+        gptr(g_phase_wave)[blockIdx.x * kPhaseWaves + w] = (unsigned long long)wall_clock64();
+}
+#else
+__device__ __forceinline__ void phase_stamp(int) {}
+__device__ __forceinline__ void phase_place() {}
+__device__ __forceinline__ void phase_wave_stamp() {}
+#endif
+
 // ------------------------------------------------------------------------------------------------
 // small device helpers
 
@@ -79,6 +113,14 @@ __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v, uint32_t edge) {
 // static LDS, so its dynamic LDS (the histogram table first) starts at address 0; the kernel checks
 // this at entry.
 __device__ __forceinline__ lds_u32 *lds_at(uint32_t byte_addr) { return (lds_u32 *)(size_t)byte_addr; }
+
+// Workgroup barrier that orders LDS accesses only: unlike __syncthreads it does not wait for the
+// wave's global loads, which stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ void lds_inc(lds_u32 *p) {
     __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -201,14 +243,15 @@ struct Packed {
 //   PACKED: one vector load of K pixels (full strips with aligned rows); unpacked when used.
 //   else:   K element loads from clamped, always valid columns; the values beyond the image are
 //           zeroed when used (ragged last strips, misaligned rows).
+// The strip's edge columns (the pixel right of the strip, and left of it for 8 neighbours) are not
+// part of a slot: a batch loads them for all its rows at once (strip_rows).
 template <typename Pix, int K, bool PACKED>
 struct RowSlot {
     static constexpr int NV = PACKED ? Packed<Pix, K>::NW : K;
     uint32_t v[NV];
-    uint32_t er, el;
 };
 
-template <typename Pix, int NB, int K, bool FULL, bool PACKED>
+template <typename Pix, int K, bool FULL, bool PACKED>
 __device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<Pix, K, PACKED> &sl) {
     constexpr int NW = Packed<Pix, K>::NW;
     // column offsets are unsigned 32-bit, so each load is a wave-uniform row address (scalar
@@ -235,10 +278,6 @@ __device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<
 #pragma unroll
         for (int k = 0; k < K; ++k) sl.v[k] = (uint32_t)rp[(uint32_t)(FULL ? c + k : min(c + k, W - 1))];
     }
-    // edge pixels: only lanes 63 (right) and 0 (left) use them, but every lane loads a valid column
-    sl.er = (uint32_t)rp[(uint32_t)(FULL ? c + K : min(c + K, W - 1))];
-    if constexpr (NB == 8) sl.el = (uint32_t)rp[(uint32_t)max(c - 1, 0)];
-    else sl.el = 0;
 }
 
 // Pixel values of a slot, multiplied by SCALE (a power of two). Values past the row end are
@@ -261,20 +300,25 @@ __device__ __forceinline__ void slot_pixels(const RowSlot<Pix, K, PACKED> &sl, i
 // ------------------------------------------------------------------------------------------------
 // per-pair accumulators (LDS)
 
-// Joint histogram of (gap d, low value lo), rows kRowStride words apart, one LDS atomic per pair:
+// Joint histogram of (gap d, low value lo), rows kRowStride words apart, one LDS atomic per pair.
+// The workgroup keeps `copies` such tables of nb + 2 rows each, one after the other; lane l adds to
+// copy l % copies, so that fewer lanes of one LDS instruction land on the same counter (same-word
+// atomics of one instruction are serialised). Rows of a copy:
 //   row 0        gap-0 pairs (at their value) and invalid pairs outside the image (at their
 //                lane's column); never read back
 //   rows 1..nb   the joint counts of (d, lo)
 //   row nb+1     lo of the pairs with d > nb (their share of hmin)
 // Pixel values arrive multiplied by 4 (kScale), so that with lo4 = 4*lo and d4 = 4*d the LDS byte
-// address of the counter is min(d4, 4*(nb+1)) * 257 + lo4: a pair costs min, sad, min and one
-// multiply-add (the table starts at LDS address 0).
+// address of the counter is (off4 + min(d4, 4*(nb+1))) * kRowStride + lo4, where off4 = 4 * the
+// first row of the lane's copy. The offset rides in the accumulator operand of the absolute
+// difference (sad), so a pair costs min, sad, min and one multiply-add whatever the copy (the table
+// starts at LDS address 0).
 // Pairs with d > nb still owe hmax and hsum; dmax tracks the lane's largest gap so that a
 // wave-uniform test after each row can run SpillAcc over that row only when some lane needs it.
 struct BandAcc {
-    lds_u32 *tab;
-    uint32_t nb;
-    uint32_t dmax;  // largest 4*d seen since the last test
+    uint32_t off4;  // 4 * first row of this lane's copy
+    uint32_t cap4;  // 4 * the large-gap row of this lane's copy: off4 + 4 * (nb + 1)
+    uint32_t dmax;  // largest off4 + 4*d seen since the last test
     static constexpr uint32_t kScale = 4;
     __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
         if (!valid) {
@@ -283,12 +327,12 @@ struct BandAcc {
             x4 = y4 = 4u * (threadIdx.x & 63u);
         }
         const uint32_t lo4 = min(x4, y4);
-        const uint32_t d4 = __builtin_amdgcn_sad_u16(x4, y4, 0u);  // |x4 - y4| (both below 2^16)
+        const uint32_t d4 = __builtin_amdgcn_sad_u16(x4, y4, off4);  // off4 + |x4 - y4| (both below 2^16)
         dmax = max(dmax, d4);
-        const uint32_t row4 = min(d4, 4u * (nb + 1u));
+        const uint32_t row4 = min(d4, cap4);
         lds_inc(lds_at(__umul24(row4, (uint32_t)kRowStride) + lo4));
     }
-    __device__ __forceinline__ bool needs_spill() const { return dmax > 4u * nb; }
+    __device__ __forceinline__ bool needs_spill() const { return dmax >= cap4; }
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
     static constexpr bool kPixels = false;
     static constexpr bool kSpill = true;
@@ -339,16 +383,17 @@ __device__ __forceinline__ TriPx prev_px(TriPx v, TriPx edge) {
     return TriPx{from_prev_lane(v.a, edge.a), from_prev_lane(v.x, edge.x)};
 }
 
-// hmax and hsum of the pairs with gap > nb (second pass over a row, rare); values scaled by 4, so
-// 4*hi and 4*(lo + hi) are already byte offsets.
+// hmax and hsum of the pairs with gap > nb (second pass over a row whose wave saw one); values
+// scaled by 4, so 4*hi and 4*(lo + hi) = x4 + y4 are already byte offsets. A pair costs the gap and
+// one compare unless it is one of the rare large gaps.
 struct SpillAcc {
     uint32_t smax, ssum;  // byte addresses of the hmax and hsum spill tables
     uint32_t nb;
     __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
-        const uint32_t a4 = min(x4, y4), b4 = max(x4, y4);
-        if (valid && b4 - a4 > 4u * nb) {
-            lds_inc(lds_at(smax + b4));
-            lds_inc(lds_at(ssum + a4 + b4));
+        const uint32_t d4 = __builtin_amdgcn_sad_u16(x4, y4, 0u);
+        if (valid && d4 > 4u * nb) {
+            lds_inc(lds_at(smax + max(x4, y4)));
+            lds_inc(lds_at(ssum + x4 + y4));
         }
     }
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
@@ -416,49 +461,78 @@ __device__ __forceinline__ void row_pairs(const P (&cur)[K], const P (&nxt)[K], 
     }
 }
 
-// Rows [r0, r1) of strip s, by one wave, in batches of kRowBatch rows: a batch issues the loads of
+// Rows a wave loads together before it uses any of them (and the halo row below), chosen so that the
+// kernel stays within 128 VGPRs (four waves per SIMD) without spilling: 16 rows when a lane's pixels
+// of a row fit one word, else 6 (each row of a batch also costs the compiler's unpacked copies), and
+// fewer where clamping or the 8-neighbourhood keep more values live. The edge pixels of all of them
+// take one VGPR per side (lane j holds row j's), so at most 63 rows.
+template <typename Pix, int NB, int K, bool CLAMP>
+constexpr int row_batch() {
+    return (K * (int)sizeof(Pix)) / 4 <= 1 ? ((CLAMP || NB == 8) ? 12 : 16) : ((CLAMP || NB == 8) ? 4 : 6);
+}
+
+// Rows [r0, r1) of strip s, by one wave, in batches of row_batch() rows: a batch issues the loads of
 // its rows and of the halo row below before it uses any of them, and uses them in order, so the
-// whole batch is in flight at once and the wait before each row only covers that row. Batches do
-// not depend on each other; other waves on the SIMD hide a batch's first load latency.
-template <typename Pix, int NB, int K, bool CLAMP, bool FULL, bool PACKED, class Acc, class Spill>
+// whole batch is in flight at once and the wait before each row only covers that row. `first` runs
+// once, after the loads of the wave's first batch are issued and before its first LDS update (the
+// single-image launch clears its tables there, so the first loads overlap the clearing).
+template <typename Pix, int NB, int K, bool CLAMP, bool FULL, bool PACKED, class Acc, class Spill, class First>
 __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
-                                           Acc &acc, Spill &spill, uint32_t &vmax) {
+                                           Acc &acc, Spill &spill, uint32_t &vmax, First &first) {
     constexpr int SW = 64 * K;
+    constexpr int B = row_batch<Pix, NB, K, CLAMP>();
     const int lane = threadIdx.x & 63;
     const Pix *base = static_cast<const Pix *>(im.ptr);
     const int64_t H = im.H, pitch = im.pitch;
     const int W = (int)im.W;
     const int c = s * SW + lane * K;
 
+    // the strip's edge columns, clamped into the image (a clamped value is never used: the pairs it
+    // would form lie outside the image and are masked)
+    const uint32_t cr = (uint32_t)min<int64_t>((int64_t)(s + 1) * SW, W - 1);
+    const uint32_t cl = (uint32_t)max(s * SW - 1, 0);
+    static_assert(B + 1 <= 64, "one lane per row of a batch holds its edge pixels");
+
     // last row a batch may touch: the halo row below the range, or the image's last row
     const int64_t rlast = min(r1, H - 1);
-    for (int64_t rb = r0; rb < r1; rb += kRowBatch) {
-        const int nr = (int)min<int64_t>(kRowBatch, r1 - rb);
-        RowSlot<Pix, K, PACKED> ring[kRowBatch + 1];
+    for (int64_t rb = r0; rb < r1; rb += B) {
+        const int nr = (int)min<int64_t>(B, r1 - rb);
+        RowSlot<Pix, K, PACKED> ring[B + 1];
+        uint32_t erv, elv = 0;
         // unconditional loads (rows past the range re-read rlast, a cache hit): with a fixed number
         // of loads in flight the compiler can wait for exactly the row it is about to use
         {
+            const int room = (int)(rlast - rb);
+            // edge pixels: lane j reads those of row rb + min(j, room)
+            const KOHLER_GLOBAL Pix *ep = gptr(base + (rb + min(lane, room)) * pitch);
+            erv = (uint32_t)ep[cr];
+            if constexpr (NB == 8) elv = (uint32_t)ep[cl];
             // row addresses by scalar increments (the rows past rlast re-read rlast)
             const Pix *rowp = base + rb * pitch;
-            const int64_t room = rlast - rb;
 #pragma unroll
-            for (int j = 0; j <= kRowBatch; ++j) {
-                load_slot<Pix, NB, K, FULL, PACKED>(rowp, c, W, ring[j]);
+            for (int j = 0; j <= B; ++j) {
+                load_slot<Pix, K, FULL, PACKED>(rowp, c, W, ring[j]);
                 if (j < room) rowp += pitch;
             }
         }
+        first();
+        // row rb + j has a row below when j < down, one above when j > 0 or rb > 0 (wave-uniform)
+        const int down = (int)min<int64_t>(B, H - 1 - rb);
+        const bool top = rb == 0;
 #pragma unroll
-        for (int j = 0; j < kRowBatch; ++j) {
+        for (int j = 0; j < B; ++j) {
             if (j < nr) {
-                const int64_t row = rb + j;
-                const bool has_down = row + 1 < H;
+                const bool has_down = j < down;
+                const bool has_up = j > 0 || !top;
                 uint32_t cur[K], nxt[K];
                 constexpr uint32_t SC = Acc::kScale;
                 slot_pixels<Pix, K, FULL, PACKED, SC>(ring[j], c, W, cur);
                 slot_pixels<Pix, K, FULL, PACKED, SC>(ring[j + 1], c, W, nxt);
-                uint32_t e0 = ((FULL || c + K < W) ? ring[j].er : 0u) * SC;
-                uint32_t e1 = ((FULL || c + K < W) ? ring[j + 1].er : 0u) * SC;
-                uint32_t l1 = ring[j + 1].el * SC;
+                const uint32_t er0 = (uint32_t)__builtin_amdgcn_readlane((int)erv, j);
+                const uint32_t er1 = (uint32_t)__builtin_amdgcn_readlane((int)erv, j + 1);
+                uint32_t e0 = ((FULL || c + K < W) ? er0 : 0u) * SC;
+                uint32_t e1 = ((FULL || c + K < W) ? er1 : 0u) * SC;
+                uint32_t l1 = (NB == 8 ? (uint32_t)__builtin_amdgcn_readlane((int)elv, j + 1) : 0u) * SC;
                 if constexpr (CLAMP) {
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
@@ -471,7 +545,7 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
                     l1 = min(l1, Mm1);
                 }
                 if constexpr (std::is_same<typename Acc::P, uint32_t>::value) {
-                    row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, acc);
+                    row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, has_up, has_down, c, W, acc);
                 } else {
                     typename Acc::P pc[K], pn[K];
 #pragma unroll
@@ -479,11 +553,11 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
                         pc[k] = Acc::prep(cur[k]);
                         pn[k] = Acc::prep(nxt[k]);
                     }
-                    row_pairs<NB, K, FULL>(pc, pn, Acc::prep(e0), Acc::prep(e1), Acc::prep(l1), row > 0, has_down,
+                    row_pairs<NB, K, FULL>(pc, pn, Acc::prep(e0), Acc::prep(e1), Acc::prep(l1), has_up, has_down,
                                            c, W, acc);
                 }
                 if constexpr (Acc::kSpill) {
-                    if (__any(acc.needs_spill())) row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, row > 0, has_down, c, W, spill);
+                    if (__any(acc.needs_spill())) row_pairs<NB, K, FULL>(cur, nxt, e0, e1, l1, has_up, has_down, c, W, spill);
                     acc.dmax = 0;
                 }
             }
@@ -492,32 +566,32 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
 }
 
 // Rows [r0, r1) of strip s of one image, by one wave.
-template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
+template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill, class First>
 __device__ __forceinline__ void strip_range(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
-                                            Acc &acc, Spill &spill, uint32_t &vmax) {
+                                            Acc &acc, Spill &spill, uint32_t &vmax, First &first) {
     constexpr int SW = 64 * K;
     if ((int64_t)(s + 1) * SW < im.W) {
         if (im.vec_ok)
-            strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
+            strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
         else
-            strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
+            strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
     } else if (im.vec_ok && im.W % K == 0) {
-        strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
+        strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
     } else {
-        strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
+        strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
     }
 }
 
 // Units [la, lb) of one image (image-local, strip-major), by one wave.
-template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
+template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill, class First>
 __device__ __forceinline__ void wave_units(const KImage &im, int64_t la, int64_t lb, uint32_t Mm1, Acc &acc,
-                                           Spill &spill, uint32_t &vmax) {
+                                           Spill &spill, uint32_t &vmax, First &first) {
     int64_t u = la;
     while (u < lb) {
         const int s = (int)(u / im.H);
         const int64_t r = u - (int64_t)s * im.H;
         const int64_t rend = min(im.H, r + (lb - u));
-        strip_range<Pix, NB, K, CLAMP>(im, s, r, rend, Mm1, acc, spill, vmax);
+        strip_range<Pix, NB, K, CLAMP>(im, s, r, rend, Mm1, acc, spill, vmax, first);
         u += rend - r;
     }
 }
@@ -568,30 +642,67 @@ __device__ __forceinline__ uint32_t lds_sum(const lds_u32 *tab, int i0, int i1, 
     return acc;
 }
 
+// Sum of n LDS words STEP words apart starting at q. n must be the same for every lane of the wave
+// (a per-lane trip count makes the compiler wait for each load before the next): eight loads are
+// issued, then added, and every load of an unrolled group is one instruction with an immediate
+// offset (STEP is a compile-time stride).
+template <int STEP>
+__device__ __forceinline__ uint32_t lds_column(const lds_u32 *q, int n) {
+    uint32_t acc = 0;
+    int k = 0;
+    for (; k + 8 <= n; k += 8, q += 8 * STEP) {
+        uint32_t t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = q[j * STEP];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc += t[j];
+    }
+    for (; k < n; ++k, q += STEP) acc += q[0];
+    return acc;
+}
+
+// Projects the banded tables (all copies) on the three marginals and adds the workgroup's D1 and E
+// to the image's accumulators. With S = kRowStride, cell (d, lo) of copy c is word (c (nb+2) + d) S + lo:
+//   hmin[v] = sum over d = 1..nb+1 of cell (d, v)   (row nb+1: the low values of the large gaps)
+//   hmax[v] = sum over d = 1..nb of cell (d, v - d), plus the large gaps' own hmax
+//   hsum[s] = sum over d = 1..nb with d = s (mod 2) of cell (d, (s - d) / 2), plus theirs
+// Column v of hmin and the diagonals of hmax and hsum step by S, S - 1 and 2S - 1 words, with the same
+// number of terms for every level: a cell (d, lo) with lo + d > 255 is never written (no pair has
+// it), and neither is a row's word 256 .. S - 1, so the terms with d > v (hmax) or d > s (hsum), which
+// land there ((d, v - d) is word (d - 1) S + (S + v - d) of the row above), add zeros. Results
+// overwrite copy 0's large-gap row (hmin) and the large-gap tables (hmax, hsum): each of those words
+// is read only by the task that writes it.
 __device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, int64_t *acc) {
-    const int M = p.M;
-    const uint32_t nb = (uint32_t)p.band;
-    constexpr uint32_t RS = kRowStride;
-    lds_u32 *tab = lds, *lospill = lds + (nb + 1u) * RS, *smax = lds + (nb + 2u) * RS, *ssum = smax + 256;
-    // project rows 1..nb of the (gap, lo) table on rows (hmin), diagonals (hmax) and anti-diagonals
-    // (hsum), adding the large-gap pairs' own counts; results overwrite lospill, smax and ssum.
-    const int inb = (int)nb;
+    const int M = p.M, nb = p.band, nc = p.copies;
+    constexpr int S = kRowStride;
+    const int cwords = (nb + 2) * S;  // words per copy
+    lds_u32 *tab = lds, *lospill = lds + (nb + 1) * S, *smax = lds + nc * cwords, *ssum = smax + 256;
     for (int x = threadIdx.x; x < 4 * M - 1; x += blockDim.x) {
         if (x < M) {
-            const int v = x;  // (d, v) for d = 1 .. nb
-            lospill[v] += lds_sum(tab, 1, inb, [&](int d) { return d * (int)RS + v; });
+            const int v = x;
+            uint32_t h = 0;
+            for (int c = 0; c < nc; ++c) h += lds_column<S>(tab + c * cwords + S + v, nb + 1);
+            lospill[v] = h;
         } else if (x < 2 * M) {
-            const int v = x - M;  // (d, v - d) for d = 1 .. min(nb, v)
-            smax[v] += lds_sum(tab, 1, min(inb, v), [&](int d) { return d * ((int)RS - 1) + v; });
+            const int v = x - M;
+            uint32_t h = smax[v];
+            for (int c = 0; c < nc; ++c) h += lds_column<S - 1>(tab + c * cwords + S + v - 1, nb);
+            smax[v] = h;
         } else {
-            const int s = x - 2 * M;  // (d, (s - d) / 2) for d = d0, d0 + 2, .. <= min(nb, s)
-            const int d0 = 2 - (s & 1);
-            const int n = min(inb, s) >= d0 ? (min(inb, s) - d0) / 2 : -1;  // last index
-            const int base = d0 * (int)RS + (s - d0) / 2;
-            ssum[s] += lds_sum(tab, 0, n, [&](int k) { return base + k * (2 * (int)RS - 1); });
+            const int sv = x - 2 * M;
+            const int d0 = 2 - (sv & 1);  // the smallest gap with the parity of sv
+            const int base = d0 * S + (sv - d0) / 2;
+            uint32_t h = ssum[sv];
+            for (int c = 0; c < nc; ++c) {
+                // nb / 2 terms for either parity, and for an odd band one more (d = nb) for odd s
+                h += lds_column<2 * S - 1>(tab + c * cwords + base, nb / 2);
+                if ((nb & 1) && (sv & 1)) h += tab[c * cwords + nb * S + (sv - nb) / 2];
+            }
+            ssum[sv] = h;
         }
     }
     __syncthreads();
+    phase_stamp(3);
     uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
         const int64_t d1 = (int64_t)lospill[v] - (int64_t)smax[v];
@@ -628,6 +739,7 @@ __device__ __forceinline__ uint64_t merge_tri(const KParams &p, lds_u32 *lds, in
         }
     }
     __syncthreads();
+    phase_stamp(3);
     uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
         const int64_t d1 = (int64_t)hmin[v] - (int64_t)hmax[v];
@@ -640,6 +752,7 @@ __device__ __forceinline__ uint64_t merge_tri(const KParams &p, lds_u32 *lds, in
 __device__ __forceinline__ uint64_t merge_marg(const KParams &p, lds_u32 *lds, int64_t *acc) {
     const int M = p.M;
     const lds_u32 *hmin = lds, *hdeg = lds + M, *hsum = lds + 2 * M;
+    phase_stamp(3);
     uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
         const int64_t d1 = 2 * (int64_t)hmin[v] - (int64_t)hdeg[v];
@@ -704,249 +817,213 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 }
 
 // ------------------------------------------------------------------------------------------------
-// One-wave finalize for M <= 256: prefix sums, C, local maxima and t0 for the image with output
-// index i. Lane l owns the thresholds 4l .. 4l+3.
-//
-// Every wave of the workgroup first sums a share of the accumulator replicas (replicas w, w + nw, ...
-// for wave w) for all 256 levels into LDS and clears what it read; after one barrier wave 0 does the
-// rest alone, with DPP scans and ballots instead of barriers. The other waves return.
+// Finalize for M <= 256: prefix sums, C, local maxima and t0 for the image with output index i, by
+// the workgroup's first four waves (wave w, lane l owns threshold t = 64 w + l); the other waves only
+// take part in the barriers.
 //
 // Local maxima: a run of equal C values starting at t (t = 0, or C(t) > C(t-1)) with C(t) > 0 is a
 // local maximum when the first change of C after t is a fall, or there is none before M.
-// t0: the largest C is found on the doubles (the division rounds correctly, so it is monotone and
-// every t with the exact largest value has the largest double); a tie between several t is settled
-// by exact comparison of sum/count, keeping the smallest t.
+// Comparisons of neighbouring C values use the doubles: the division rounds correctly, so it is
+// monotone, and two different doubles order their exact values the same way; equal doubles of a
+// positive C are settled exactly (128-bit cross products). t0: the largest double marks every t
+// with the exact largest C (and maybe others that round to it); a tie between several t is settled
+// exactly, keeping the smallest t.
 
-constexpr int kWaveT = 4;          // thresholds per lane
-constexpr int kWaveMaxM = 64 * kWaveT;
+constexpr int kFinWaves = 4;
+constexpr int kFinMaxM = 64 * kFinWaves;
 
-__device__ __forceinline__ void finalize_wave(const KParams &p, int i, lds_u32 *lds) {
-    const int M = p.M, R = p.nrep, nw = blockDim.x >> 6;
+struct FinScratch {
+    int64_t tot[kFinWaves][3];  // per wave: sums of D1, E and v * E over its levels
+    uint64_t ne[kFinWaves];     // per wave: levels where C changes (C(t) != C(t-1))
+    uint64_t fa[kFinWaves];     // per wave: levels where C falls
+    uint64_t cmax[kFinWaves];   // per wave: largest C as bits (C >= 0, so bits order as values)
+    uint64_t mx[kFinWaves];     // per wave: local maxima
+    uint64_t cand[kFinWaves];   // per wave: levels whose C equals the largest double
+    int64_t sm[kFinMaxM], cnt[kFinMaxM];  // the curve, for the rare exact tie-break of t0
+};
+
+__device__ __forceinline__ uint64_t dbits(double x) { return (uint64_t)__double_as_longlong(x); }
+
+// Lane l receives lane l-1's double; lane 0 receives 0.
+__device__ __forceinline__ double prev_lane_f64(double x) {
+    return __longlong_as_double(prev_lane64((int64_t)dbits(x)));
+}
+
+__device__ __forceinline__ void finalize_small(const KParams &p, int i, lds_u32 *lds) {
+    const int M = p.M, R = p.nrep;
     const int lane = threadIdx.x & 63;
     const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const bool active = w < kFinWaves;  // wave-uniform
+    const int t = 64 * w + lane;
+    const bool in = active && t < M;
     const int64_t RS = p.rep_stride;
     const bool packed = p.packed_acc != 0;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * p.acc_stride);
-    KOHLER_LDS int64_t *part = reinterpret_cast<KOHLER_LDS int64_t *>(lds);  // [nw][2][256]
-    const int tb = kWaveT * lane;
+    KOHLER_LDS FinScratch &fs = *reinterpret_cast<KOHLER_LDS FinScratch *>(lds);
 
-    // 1. replica sums, a share per wave; a wave issues all its loads before it uses any (levels past
-    //    M re-read a valid word and are dropped), then clears the words it read
-    {
-        constexpr int kRepsPerWave = kMaxReplicas / 4;  // blockDim.x >= 256
-        // sum of this wave's replicas of the array starting at word `base` of each replica
-        auto gather = [&](int base, int64_t (&s)[kWaveT]) {
-            uint64_t v[kRepsPerWave][kWaveT];
-#pragma unroll
-            for (int k = 0; k < kRepsPerWave; ++k) {
-                const int r = w + k * nw;
-                if (r < R) {  // wave-uniform: a wave loads only the replicas it sums
-#pragma unroll
-                    for (int q = 0; q < kWaveT; ++q)
-                        v[k][q] = load_shared(acc + r * RS + base + (tb + q < M ? tb + q : 0));
-                } else {
-#pragma unroll
-                    for (int q = 0; q < kWaveT; ++q) v[k][q] = 0;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < kWaveT; ++q) s[q] = 0;
-#pragma unroll
-            for (int k = 0; k < kRepsPerWave; ++k) {
-                const bool use = w + k * nw < R;
-#pragma unroll
-                for (int q = 0; q < kWaveT; ++q) s[q] += use ? (int64_t)v[k][q] : 0;
-            }
-        };
-        int64_t s0[kWaveT], s1[kWaveT] = {0, 0, 0, 0};
-        gather(0, s0);
-        if (!packed) gather(M, s1);  // images with 2^30 or more pairs only
-#pragma unroll
-        for (int k = 0; k < kRepsPerWave; ++k) {
-            const int r = w + k * nw;
-            if (r < R) {
-#pragma unroll
-                for (int q = 0; q < kWaveT; ++q) {
-                    if (tb + q < M) {
-                        store_shared(acc + r * RS + tb + q, 0);
-                        if (!packed) store_shared(acc + r * RS + M + tb + q, 0);
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < kWaveT; ++q) {
-            part[(2 * w) * kWaveMaxM + tb + q] = s0[q];
-            part[(2 * w + 1) * kWaveMaxM + tb + q] = s1[q];
-        }
-    }
-    __syncthreads();
-    if (w != 0) return;
-
+    // 1. D1 and E of level t: the sum of the replicas (all loads issued before any is used), then
+    //    the words are cleared for the next launch
+    int64_t d1 = 0, e = 0;
     uint32_t rf = 0;
-    if (lane == 0) rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
-
-    // 2. D1 and E of this lane's levels
-    int64_t d1[kWaveT], e[kWaveT];
+    if (active) {
+        const int tt = in ? t : 0;
+        // rounds of kGather loads, issued together (replica indices past R re-read the last one and
+        // are dropped): one memory latency per round, and a single round for R <= kGather
+        constexpr int kGather = 8;
+        uint64_t s0 = 0, s1 = 0;
+        // the range flag is read by every lane of the wave with the replicas (a single-lane load
+        // would be waited for inside its branch) and used only at the end
+        rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
+        for (int rb = 0; rb < R; rb += kGather) {
+            uint64_t v[kGather];
 #pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        int64_t a = 0, b = 0;
+            for (int j = 0; j < kGather; ++j) v[j] = load_shared(acc + min(rb + j, R - 1) * RS + tt);
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {  // blockDim.x <= 512: at most 8 waves
-            const int64_t pa = part[(2 * min(v, nw - 1)) * kWaveMaxM + tb + q];
-            const int64_t pb = part[(2 * min(v, nw - 1) + 1) * kWaveMaxM + tb + q];
-            a += v < nw ? pa : 0;
-            b += v < nw ? pb : 0;
+            for (int j = 0; j < kGather; ++j) s0 += rb + j < R ? v[j] : 0ull;
+        }
+        if (!packed) {  // images with 2^30 or more pairs: E has words of its own
+            for (int rb = 0; rb < R; rb += kGather) {
+                uint64_t v[kGather];
+#pragma unroll
+                for (int j = 0; j < kGather; ++j) v[j] = load_shared(acc + min(rb + j, R - 1) * RS + M + tt);
+#pragma unroll
+                for (int j = 0; j < kGather; ++j) s1 += rb + j < R ? v[j] : 0ull;
+            }
+        }
+        if (in) {
+            for (int r = 0; r < R; ++r) {
+                store_shared(acc + r * RS + t, 0);
+                if (!packed) store_shared(acc + r * RS + M + t, 0);
+            }
         }
         if (packed) {
             // E * 2^32 + D1 summed as one word: |D1| < 2^31 because the image has < 2^30 pairs
-            d1[q] = (int64_t)(int32_t)(uint32_t)(uint64_t)a;
-            e[q] = (a - d1[q]) >> 32;
+            d1 = (int64_t)(int32_t)(uint32_t)s0;
+            e = (int64_t)(s0 - (uint64_t)d1) >> 32;
         } else {
-            d1[q] = a;
-            e[q] = b;
+            d1 = (int64_t)s0;
+            e = (int64_t)s1;
         }
-        if (tb + q >= M) d1[q] = e[q] = 0;
+        if (!in) d1 = e = 0;
     }
+    phase_stamp(6);
 
-    // 3. count = prefix of D1; with P0 = prefix of E and P1 = prefix of v*E, sum(t) = (t+1) P0 - P1
-    int64_t c0[kWaveT], c1[kWaveT], c2[kWaveT];
-    int64_t r0 = 0, r1 = 0, r2 = 0;
-#pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        r0 += d1[q];
-        r1 += e[q];
-        r2 += (int64_t)(tb + q) * e[q];
-        c0[q] = r0;
-        c1[q] = r1;
-        c2[q] = r2;
+    // 2. count = prefix of D1; with P0 = prefix of E and P1 = prefix of v E, sum(t) = (t+1) P0 - P1
+    const int64_t x0 = wave_iscan(d1), x1 = wave_iscan(e), x2 = wave_iscan((int64_t)t * e);
+    if (active && lane == 63) {
+        fs.tot[w][0] = x0;
+        fs.tot[w][1] = x1;
+        fs.tot[w][2] = x2;
     }
-    const int64_t x0 = wave_iscan(r0) - r0, x1 = wave_iscan(r1) - r1, x2 = wave_iscan(r2) - r2;
-    int64_t sm[kWaveT], cnt[kWaveT];
-#pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        cnt[q] = x0 + c0[q];
-        sm[q] = (int64_t)(tb + q + 1) * (x1 + c1[q]) - (x2 + c2[q]);
+    __syncthreads();
+    int64_t c0 = 0, c1 = 0, c2 = 0;  // totals of the waves before this one
+    for (int v = 0; v < w && v < kFinWaves; ++v) {
+        c0 += fs.tot[v][0];
+        c1 += fs.tot[v][1];
+        c2 += fs.tot[v][2];
     }
+    const int64_t cnt = c0 + x0;
+    const int64_t sm = (int64_t)(t + 1) * (c1 + x1) - (c2 + x2);
+    const double C = cnt ? (double)sm / (double)cnt : 0.0;
 
-    // 4. relation of C(t) to C(t-1), positivity, and the masks over all levels
-    const int64_t ps = prev_lane64(sm[kWaveT - 1]), pk = prev_lane64(cnt[kWaveT - 1]);
-    int rel[kWaveT];
-    uint64_t NE[kWaveT], FA[kWaveT], ST[kWaveT];
-#pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        const int t = tb + q;
-        const bool valid = t < M;
-        rel[q] = (t == 0 || !valid) ? 0 : cmp_curve(sm[q], cnt[q], q ? sm[q - 1] : ps, q ? cnt[q - 1] : pk);
-        NE[q] = __ballot(rel[q] != 0);
-        FA[q] = __ballot(rel[q] < 0);
-        ST[q] = __ballot(valid && sm[q] > 0 && (t == 0 || rel[q] > 0));
+    // 3. sign of C(t) - C(t-1): the previous level from the previous lane, or for lane 0 from the
+    //    totals of the earlier waves (level 64 w - 1)
+    int64_t ps = prev_lane64(sm), pk = prev_lane64(cnt);
+    double pC = prev_lane_f64(C);
+    if (lane == 0) {
+        ps = (int64_t)(64 * w) * c1 - c2;
+        pk = c0;
+        pC = pk ? (double)ps / (double)pk : 0.0;
     }
-    const uint64_t ne_any = NE[0] | NE[1] | NE[2] | NE[3];
-    const uint64_t later = lane == 63 ? 0ull : ne_any & (~0ull << (lane + 1));
-    // first change after this lane's levels: 1 = fall, 0 = rise, -1 = none before M
-    int next_fall = -1;
+    int rel = 0;
+    if (in && t > 0) {
+        rel = C > pC ? 1 : (C < pC ? -1 : 0);
+        if (rel == 0 && sm != 0) rel = cmp_curve(sm, cnt, ps, pk);  // equal doubles: exact order
+    }
+    const uint64_t NE = __ballot(rel != 0), FA = __ballot(rel < 0);
+    const bool start = in && sm > 0 && (t == 0 || rel > 0);
+    const uint64_t cmax_w = readlane64(wave_imax(in ? dbits(C) : 0ull), 63);
+    if (active && lane == 0) {
+        fs.ne[w] = NE;
+        fs.fa[w] = FA;
+        fs.cmax[w] = cmax_w;
+    }
+    if (in) {
+        fs.sm[t] = sm;
+        fs.cnt[t] = cnt;
+    }
+    __syncthreads();
+
+    // 4. local maxima: the first change after t, in this wave or in a later one
+    int next = -1;  // 1: fall, 0: rise, -1: no change before M
+    const uint64_t later = lane == 63 ? 0ull : NE & (~0ull << (lane + 1));
     if (later) {
-        const int l2 = __builtin_ctzll(later);
-        const int q2 = ((NE[0] >> l2) & 1) ? 0 : ((NE[1] >> l2) & 1) ? 1 : ((NE[2] >> l2) & 1) ? 2 : 3;
-        next_fall = (int)((FA[q2] >> l2) & 1);
+        next = (int)((FA >> __builtin_ctzll(later)) & 1ull);
+    } else {
+        for (int v = w + 1; v < kFinWaves; ++v) {
+            const uint64_t nv = fs.ne[v];
+            if (nv) {
+                next = (int)((fs.fa[v] >> __builtin_ctzll(nv)) & 1ull);
+                break;
+            }
+        }
     }
-    bool is_max[kWaveT];
+    const bool is_max = start && next != 0;
+    const uint64_t MX = __ballot(is_max);
+    uint64_t cmax = 0;
 #pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        int nf = next_fall;  // first change after level q: look inside the lane first
-#pragma unroll
-        for (int q2 = kWaveT - 1; q2 > q; --q2)
-            if (rel[q2] != 0) nf = rel[q2] < 0 ? 1 : 0;
-        is_max[q] = ((ST[q] >> lane) & 1) && nf != 0;
+    for (int v = 0; v < kFinWaves; ++v) cmax = max(cmax, fs.cmax[v]);
+    const uint64_t CA = __ballot(in && cmax != 0 && dbits(C) == cmax);
+    if (active && lane == 0) {
+        fs.mx[w] = MX;
+        fs.cand[w] = CA;
     }
+    __syncthreads();
 
-    // 5. compaction of the maxima in ascending order
-    uint64_t MX[kWaveT];
-    uint32_t below = 0, found = 0;
+    // 5. compaction of the maxima in ascending order, and t0
+    uint32_t below = 0, found = 0, ncand = 0;
 #pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        MX[q] = __ballot(is_max[q]);
-        below += lanes_below(MX[q]);
-        found += (uint32_t)__builtin_popcountll(MX[q]);
+    for (int v = 0; v < kFinWaves; ++v) {
+        const uint32_t nv = (uint32_t)__builtin_popcountll(fs.mx[v]);
+        below += v < w ? nv : 0u;
+        found += nv;
+        ncand += (uint32_t)__builtin_popcountll(fs.cand[v]);
     }
     int32_t *othr = p.thr + (int64_t)i * p.thr_stride;
-    uint32_t own = 0;
-#pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        if (is_max[q]) {
-            const uint32_t pos = below + own;
-            if ((int64_t)pos < (int64_t)p.cap) othr[pos] = tb + q;
-            ++own;
-        }
+    if (is_max) {
+        const uint32_t pos = below + lanes_below(MX);
+        if ((int64_t)pos < (int64_t)p.cap) othr[pos] = t;
     }
-
-    // 6. C, and t0
-    double C[kWaveT];
-    uint64_t cb = 0;
-#pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        C[q] = cnt[q] ? (double)sm[q] / (double)cnt[q] : 0.0;
-        if (tb + q < M) cb = max(cb, (uint64_t)__double_as_longlong(C[q]));  // C >= 0: bits order as values
+    if (in) {
+        p.sum[(int64_t)i * p.ostride + t] = sm;
+        p.count[(int64_t)i * p.ostride + t] = cnt;
+        p.C[(int64_t)i * p.ostride + t] = C;
     }
-    const uint64_t cmax = readlane64(wave_imax(cb), 63);
-    int32_t t0 = -1;
-    if (cmax != 0) {
-        uint64_t CA[kWaveT];
-        uint32_t ncand = 0;
-#pragma unroll
-        for (int q = 0; q < kWaveT; ++q) {
-            CA[q] = __ballot(tb + q < M && (uint64_t)__double_as_longlong(C[q]) == cmax);
-            ncand += (uint32_t)__builtin_popcountll(CA[q]);
-        }
-        if (ncand == 1) {
-#pragma unroll
-            for (int q = 0; q < kWaveT; ++q)
-                if (CA[q]) t0 = kWaveT * __builtin_ctzll(CA[q]) + q;
-        } else {
-            // several levels share the largest double: compare them exactly, in ascending t
-            KOHLER_LDS int64_t *ts = part, *tk = part + kWaveMaxM;
-#pragma unroll
-            for (int q = 0; q < kWaveT; ++q) {
-                ts[tb + q] = sm[q];
-                tk[tb + q] = cnt[q];
-            }
-            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS writes are done
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) {
-                int64_t bs_ = 0, bk_ = 0;
-                for (int t = 0; t < M; ++t) {
-                    if (!((CA[t % kWaveT] >> (t / kWaveT)) & 1)) continue;
-                    if (t0 < 0 || cmp_curve(ts[t], tk[t], bs_, bk_) > 0) {
-                        t0 = t;
-                        bs_ = ts[t];
-                        bk_ = tk[t];
-                    }
+    if (w == 0 && lane == 0) {
+        int32_t t0 = -1;
+        int64_t bs_ = 0, bk_ = 0;
+        for (int v = 0; v < kFinWaves; ++v) {
+            for (uint64_t m = fs.cand[v]; m; m &= m - 1) {
+                const int tc = 64 * v + __builtin_ctzll(m);
+                if (t0 < 0) {
+                    t0 = tc;
+                    bs_ = fs.sm[tc];
+                    bk_ = fs.cnt[tc];
+                    if (ncand == 1) break;
+                } else if (cmp_curve(fs.sm[tc], fs.cnt[tc], bs_, bk_) > 0) {
+                    t0 = tc;
+                    bs_ = fs.sm[tc];
+                    bk_ = fs.cnt[tc];
                 }
             }
-            t0 = __builtin_amdgcn_readfirstlane(t0);
         }
-    }
-
-    // 7. outputs and counters for the next launch
-    int64_t *osum = p.sum + (int64_t)i * p.ostride;
-    int64_t *ocnt = p.count + (int64_t)i * p.ostride;
-    double *oC = p.C + (int64_t)i * p.ostride;
-#pragma unroll
-    for (int q = 0; q < kWaveT; ++q) {
-        if (tb + q < M) {
-            osum[tb + q] = sm[q];
-            ocnt[tb + q] = cnt[q];
-            oC[tb + q] = C[q];
-        }
-    }
-    if (lane == 0) {
         __hip_atomic_store(gptr(p.rflag + i), 0u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
         store_shared(p.done + i, 0);
         p.n_thr[(int64_t)i * p.istride] = (int32_t)found;
         p.t0[(int64_t)i * p.istride] = t0;
         p.status[(int64_t)i * p.istride] = rf ? ST_RANGE : ((int64_t)found > (int64_t)p.cap ? ST_CAPACITY : ST_OK);
     }
+    phase_stamp(7);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1171,12 +1248,17 @@ __device__ __forceinline__ KImage image_desc(const KParams &p, int i) {
     return im;
 }
 
+// Largest workgroup of an instance: 1024 threads where the registers fit four waves per SIMD without
+// spilling, else 512 (the marginal form and the 8-neighbourhood with 8 pixels per lane).
+template <int NB, int K, int FORM>
+constexpr int max_block() { return (FORM == FORM_MARG || (NB == 8 && K == 8)) ? 512 : 1024; }
+
 template <typename Pix, int NB, int K, int FORM, bool CLAMP>
-__global__ void __launch_bounds__(512) curve_kernel(KParams p) {
+__global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KParams p) {
     extern __shared__ __align__(16) uint32_t lds_raw[];
     lds_u32 *lds = (lds_u32 *)lds_raw;
     LdsScratch &bs = *reinterpret_cast<LdsScratch *>(
-        reinterpret_cast<KOHLER_LDS uint8_t *>(lds) + lds_main_bytes(FORM, p.M, p.band, (int)blockDim.x));
+        reinterpret_cast<KOHLER_LDS uint8_t *>(lds) + lds_main_bytes(FORM, p.M, p.band, (int)blockDim.x, p.copies));
 
     if ((uint32_t)(size_t)lds != 0u) {
         // the LDS layout assumption behind lds_at() does not hold: report, compute nothing
@@ -1184,13 +1266,16 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
             for (int i = 0; i < p.n; ++i) p.status[(int64_t)image_desc_out(p, i) * p.istride] = ST_LAYOUT;
         return;
     }
+    phase_stamp(0);
+    phase_place();
     const int G = gridDim.x;
     // consecutive logical workgroups land on the same XCD (the dispatcher deals blocks round-robin)
     const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
     const uint32_t Mm1 = (uint32_t)p.M - 1u;
 
     uint32_t table_words;
-    if constexpr (FORM == FORM_BAND) table_words = (((uint32_t)p.band + 2u) * kRowStride + 768u + 3u) & ~3u;
+    if constexpr (FORM == FORM_BAND)
+        table_words = ((uint32_t)p.copies * ((uint32_t)p.band + 2u) * kRowStride + 768u + 3u) & ~3u;
     else if constexpr (FORM == FORM_TRI) table_words = (tri_words((uint32_t)p.M) + 64u + 3u) & ~3u;
     else table_words = 4u * (uint32_t)p.M;
 
@@ -1198,7 +1283,8 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         for (uint32_t x = threadIdx.x; x < table_words / 4; x += blockDim.x)
             reinterpret_cast<KOHLER_LDS u32x4 *>(lds)[x] = u32x4{0u, 0u, 0u, 0u};
         if (threadIdx.x == 0) bs.next = 0;
-        __syncthreads();
+        lds_barrier();
+        phase_stamp(1);
     };
 
     // Runs `chunks(acc, spill, vmax)` with the accumulators of this kernel's form; it must feed every
@@ -1206,9 +1292,11 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
     auto accumulate = [&](auto &&chunks) -> uint32_t {
         uint32_t vmax = 0;
         if constexpr (FORM == FORM_BAND) {
-            const uint32_t nb = (uint32_t)p.band;
-            BandAcc acc{lds, nb, 0u};
-            SpillAcc spill{4u * (nb + 2u) * kRowStride, 4u * ((nb + 2u) * kRowStride + 256u), nb};
+            const uint32_t nb = (uint32_t)p.band, rows = nb + 2u;
+            const uint32_t off4 = 4u * rows * ((threadIdx.x & 63u) % (uint32_t)p.copies);
+            BandAcc acc{off4, off4 + 4u * (nb + 1u), 0u};
+            const uint32_t spill0 = 4u * (uint32_t)p.copies * rows * kRowStride;
+            SpillAcc spill{spill0, spill0 + 4u * 256u, nb};
             chunks(acc, spill, vmax, Mm1 * BandAcc::kScale);
             vmax /= BandAcc::kScale;
         } else if constexpr (FORM == FORM_TRI) {
@@ -1220,12 +1308,14 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
             SpillAcc spill{0u, 0u, 0u};  // not used by the marginal form
             chunks(acc, spill, vmax, Mm1);
         }
+        phase_wave_stamp();
         return vmax;
     };
 
-    // After the pair work of `units` units of image im: range flag, merge into the image's
-    // accumulators, ticket, and the finalize step when this workgroup completed the image.
-    auto flush = [&](const KImage &im, uint32_t vmax, int64_t units) {
+    // After the pair work of `units` units of image im (of `expected` in the whole launch, counted in
+    // the ticket): range flag, merge into the image's accumulators, ticket, and the finalize step
+    // when this workgroup completed the image.
+    auto flush = [&](const KImage &im, uint32_t vmax, int64_t units, int64_t expected) {
         const int i = im.out;
         uint64_t sink = 0;
         if constexpr (CLAMP) {
@@ -1234,6 +1324,7 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
                 sink = __hip_atomic_fetch_or(gptr(p.rflag + i), 1u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
         }
         __syncthreads();
+        phase_stamp(2);
         if (units == 0) return;  // uniform: nothing to add, and no ticket to take
         int64_t *acc_g = p.acc + (int64_t)i * p.acc_stride + (int64_t)(blockIdx.x % (uint32_t)p.nrep) * p.rep_stride;
         if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
@@ -1245,74 +1336,42 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
         asm volatile("" ::"v"((uint32_t)sink), "v"((uint32_t)(sink >> 32)));
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
+        phase_stamp(4);
         if (threadIdx.x == 0) {
             const unsigned long long old = add_shared(p.done + i, (unsigned long long)units);
-            bs.last = (old + (unsigned long long)units == (unsigned long long)im.nunits) ? 1 : 0;
+            bs.last = (old + (unsigned long long)units == (unsigned long long)expected) ? 1 : 0;
         }
         __syncthreads();
+        phase_stamp(5);
         if (bs.last) {
             if constexpr (FORM == FORM_MARG) {
-                if (p.M <= kWaveMaxM) finalize_wave(p, i, lds);
+                if (p.M <= kFinMaxM) finalize_small(p, i, lds);
                 else finalize(p, i, lds, bs);
             } else {
-                finalize_wave(p, i, lds);
+                finalize_small(p, i, lds);
             }
         }
         __syncthreads();
     };
 
     if (p.dyn) {
-        // One image: a chunk is kChunk consecutive rows of one strip. Chunks are numbered row-block
-        // major (chunk c covers strip c mod nstrips of row block c / nstrips), so neighbouring
-        // strips of the same rows get consecutive numbers, and they are dealt round-robin to the
-        // workgroups (chunk c to logical workgroup c mod G): every workgroup samples the whole image,
-        // costly regions (many large-gap pairs) spread evenly, and the next strip's first column,
-        // which a strip's rows also read, is fetched at about the same time by a workgroup on the
-        // same XCD (shared L2). Waves claim their workgroup's chunks in turn.
+        // One image, static work: the launch's Q waves split the image's units (rows of strips,
+        // strip-major) into Q contiguous ranges, and wave w of logical workgroup g takes range
+        // w * G + g. The ranges of one workgroup (and of one SIMD) lie far apart in the image, so
+        // costly regions (many large-gap pairs) spread over the compute units. The tables are
+        // cleared first: a barrier after the first loads would wait until every wave has issued
+        // them, which the opening burst of requests throttles. The ticket counts waves.
         const KImage im = image_desc(p, 0);
-        const int64_t ns = im.nstrips;
-        const int64_t nblocks = (im.H + kChunk - 1) / kChunk;
-        const int64_t nchunks = nblocks * ns;
-        // number of chunks c < n with c = g (mod G)
-        auto upto = [&](int64_t n) -> int64_t { return n > g ? (n - g - 1) / G + 1 : 0; };
-        const int64_t mine = upto(nchunks);  // chunks of this workgroup
+        const int nw = (int)(blockDim.x >> 6);
+        const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int64_t Q = (int64_t)G * nw, q = (int64_t)w * G + g;
+        const int64_t ua = q * im.nunits / Q, ub = (q + 1) * im.nunits / Q;
         clear_tables();
-        auto claim = [&]() -> uint32_t {
-            uint32_t k = 0;
-            if ((threadIdx.x & 63) == 0)
-                k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            return (uint32_t)__builtin_amdgcn_readfirstlane(k);
-        };
+        auto nothing = []() {};
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
-            // chunk numbers stay below 2^32 (at most 2^40 pixels, chunks of kChunk rows by at least 256
-            // columns),
-            // so the decode is a 32-bit division by a wave-uniform value
-            //
-            // The workgroup's last chunks are claimed in pieces of kTailRows rows (a quarter of its
-            // waves' worth of chunks), so that its waves finish closer together.
-            const uint32_t ntail = (uint32_t)min<int64_t>(mine, (int64_t)(blockDim.x >> 8));
-            const uint32_t whole = (uint32_t)mine - ntail;
-            constexpr uint32_t kPieces = kChunk / kTailRows;
-            const uint32_t nclaims = whole + ntail * kPieces;
-            for (uint32_t j = claim(); j < nclaims; j = claim()) {
-                uint32_t jc = j, off = 0, len = kChunk;
-                if (j >= whole) {
-                    jc = whole + (j - whole) / kPieces;
-                    off = ((j - whole) % kPieces) * kTailRows;
-                    len = kTailRows;
-                }
-                const uint32_t c = (uint32_t)g + jc * (uint32_t)G;
-                const uint32_t blk = c / (uint32_t)ns, strip = c - blk * (uint32_t)ns;
-                const int64_t r0 = (int64_t)blk * kChunk + off;
-                if (r0 < im.H)  // a piece past the last row of a short final row block is empty
-                    strip_range<Pix, NB, K, CLAMP>(im, (int)strip, r0, min(im.H, r0 + (int64_t)len), mm1, acc,
-                                                   spill, vm);
-            }
+            wave_units<Pix, NB, K, CLAMP>(im, ua, ub, mm1, acc, spill, vm, nothing);
         });
-        // units of this workgroup: kChunk rows per chunk, less the short chunks of the last row block
-        const int64_t last_rows = im.H - (nblocks - 1) * kChunk;
-        const int64_t units = mine * kChunk - (upto(nchunks) - upto(nchunks - ns)) * (kChunk - last_rows);
-        flush(im, vmax, units);
+        flush(im, vmax, nw, Q);
         return;
     }
 
@@ -1335,13 +1394,14 @@ __global__ void __launch_bounds__(512) curve_kernel(KParams p) {
                 k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return (uint32_t)__builtin_amdgcn_readfirstlane(k);
         };
+        auto nothing = []() {};
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
             for (uint32_t k = claim(); k < nchunks; k = claim()) {
                 const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
-                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
+                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm, nothing);
             }
         });
-        flush(im, vmax, nseg);
+        flush(im, vmax, nseg, im.nunits);
         u = seg_end;
     }
 }
@@ -1376,15 +1436,15 @@ hipError_t allow_large_lds(const void *kern) {
 }  // namespace
 
 hipError_t curve_kernel_for(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block,
-                            const void **func, size_t *lds) {
-    *lds = lds_bytes(form, M, band, block);
+                            int copies, const void **func, size_t *lds) {
+    *lds = lds_bytes(form, M, band, block, copies);
     *func = pick_kernel(dtype, nbhd, form, px_per_lane, M);
     return allow_large_lds(*func);
 }
 
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,
                         int grid, hipStream_t stream) {
-    const size_t lds = lds_bytes(form, p.M, p.band, block);
+    const size_t lds = lds_bytes(form, p.M, p.band, block, p.copies);
     const void *kern = pick_kernel(dtype, nbhd, form, px_per_lane, p.M);
     hipError_t e = allow_large_lds(kern);
     if (e != hipSuccess) return e;
@@ -1395,13 +1455,44 @@ hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_
     return hipGetLastError();
 }
 
-int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block) {
+int max_block_for(int dtype, int nbhd, int form, int px_per_lane, int M) {
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, pick_kernel(dtype, nbhd, form, px_per_lane, M)) != hipSuccess) return 0;
+    return a.maxThreadsPerBlock;
+}
+
+int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block, int copies) {
     const void *kern = pick_kernel(dtype, nbhd, form, px_per_lane, M);
     if (allow_large_lds(kern) != hipSuccess) return 1;
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds_bytes(form, M, band, block)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds_bytes(form, M, band, block, copies)) !=
+        hipSuccess)
         return 1;
     return n > 0 ? n : 1;
 }
 
 }  // namespace kohler
+
+#ifdef KOHLER_PHASE_CLOCK
+// Measurement build only: copy (and optionally clear) the phase timestamps of the last launches.
+// `slots` receives kPhaseMaxWG * kPhaseSlots words, `waves` kPhaseMaxWG * kPhaseWaves words.
+extern "C" __attribute__((visibility("default"))) int kohler_phase_clock_read(unsigned long long *slots,
+                                                                               unsigned long long *waves,
+                                                                               int clear) {
+    using namespace kohler;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess && slots)
+        e = hipMemcpyFromSymbol(slots, HIP_SYMBOL(g_phase), sizeof(g_phase), 0, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && waves)
+        e = hipMemcpyFromSymbol(waves, HIP_SYMBOL(g_phase_wave), sizeof(g_phase_wave), 0, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && clear) {
+        void *a = nullptr, *b = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(g_phase));
+        if (e == hipSuccess) e = hipGetSymbolAddress(&b, HIP_SYMBOL(g_phase_wave));
+        if (e == hipSuccess) e = hipMemset(a, 0, sizeof(g_phase));
+        if (e == hipSuccess) e = hipMemset(b, 0, sizeof(g_phase_wave));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    return e == hipSuccess ? 0 : -5;
+}
+#endif

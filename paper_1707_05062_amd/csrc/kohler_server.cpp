@@ -133,7 +133,7 @@ struct Launch {
 
 // A graph is specific to an image shape, whether the image is already on the device, the lane and
 // the launch plan; buffers and the slot are updated in the instantiated graph before each replay.
-typedef std::tuple<int64_t, int64_t, int64_t, int, int, int, int, int, int, int, int> GraphKey;
+typedef std::tuple<int64_t, int64_t, int64_t, int, int, int, int, int, int, int, int, int> GraphKey;
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -197,6 +197,7 @@ KParams slot_params(const kohler_server *s, const kohler_plan &pl) {
     KParams p{};
     p.M = s->cfg.M;
     p.band = pl.band;
+    p.copies = pl.copies;
     p.cap = s->cfg.thr_capacity;
     p.nrep = pl.replicas;
     p.rep_stride = s->rstride;
@@ -242,7 +243,8 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
     if (n == 1 && c.use_graphs && (s->graphs.size() < kMaxGraphs ||
                                    s->graphs.count(GraphKey(items[0].H, items[0].W, items[0].pitch,
                                                             items[0].on_device, lane, pl.form, pl.band,
-                                                            pl.block, pl.grid, pl.px_per_lane, pl.replicas)))) {
+                                                            pl.block, pl.grid, pl.px_per_lane, pl.replicas,
+                                                            pl.copies)))) {
         const Item &it = items[0];
         p.n = 1;
         p.dyn = 1;
@@ -250,8 +252,8 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
         p.img0.out = it.slot;
         const void *func = nullptr;
         size_t lds = 0;
-        if ((e = curve_kernel_for(c.dtype, c.nbhd, pl.form, pl.px_per_lane, c.M, pl.band, pl.block, &func,
-                                  &lds)) != hipSuccess)
+        if ((e = curve_kernel_for(c.dtype, c.nbhd, pl.form, pl.px_per_lane, c.M, pl.band, pl.block, pl.copies,
+                                  &func, &lds)) != hipSuccess)
             return pick_status(e);
         KParams arg = p;
         void *argv[1] = {&arg};
@@ -267,7 +269,7 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
         void *img_dst = s->arena_base + it.arena_off;
 
         const GraphKey key(it.H, it.W, it.pitch, it.on_device ? 1 : 0, lane, pl.form, pl.band, pl.block,
-                           pl.grid, pl.px_per_lane, pl.replicas);
+                           pl.grid, pl.px_per_lane, pl.replicas, pl.copies);
         auto found = s->graphs.find(key);
         if (found == s->graphs.end()) {
             GraphEntry g;

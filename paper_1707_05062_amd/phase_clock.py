@@ -1,0 +1,117 @@
+"""Per-phase breakdown of one curve launch, from the measurement build ``libkohler_phase.so``.
+
+Build it first on the CPU (``python -m paper_1707_05062_amd.build --phase-clock``), then run
+``python -m paper_1707_05062_amd.phase_clock`` on the GPU. Every workgroup of the curve kernel
+records the 100 MHz real-time counter at its phase boundaries (entry, LDS tables cleared, pair work
+done, merge atomics issued, merge atomics performed, ticket taken; the finishing workgroup also after
+gathering the accumulator replicas and at its end) and each wave the end of its pair work. The script
+launches the kernel on the 3456x5184 u8 image (M = 256, N4) over rotated buffers, reads the stamps
+after each launch and prints a Markdown summary (medians over the launches, in microseconds).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SLOTS, MAXWG, WAVES = 12, 4096, 16
+TICK_US = 0.01  # the real-time counter runs at 100 MHz
+
+
+def breakdown(slots: np.ndarray, waves: np.ndarray, grid: int, nwaves: int) -> dict:
+    s = slots.reshape(MAXWG, SLOTS)[:grid].astype(np.int64)
+    w = waves.reshape(MAXWG, WAVES)[:grid, :nwaves].astype(np.int64)
+    fin = np.nonzero(s[:, 7])[0]
+    assert len(fin) == 1, f"expected one finishing workgroup, found {len(fin)}"
+    f = int(fin[0])
+    t0 = s[:, 0].min()
+    us = lambda x: float(x) * TICK_US  # noqa: E731
+    # placement: compute unit = (XCD, engine, shader array, unit) from the hardware id registers
+    hw, xcc = s[:, 8], s[:, 9]
+    cu = (xcc & 0xF) * 4096 + ((hw >> 13) & 7) * 512 + ((hw >> 12) & 1) * 256 + ((hw >> 8) & 0xF)
+    _, per_cu = np.unique(cu, return_counts=True)
+    return {
+        "compute_units_used": float(len(per_cu)),
+        "max_workgroups_per_cu": float(per_cu.max()),
+        "span": us(s[f, 7] - t0),
+        "dispatch_spread": us(s[:, 0].max() - t0),
+        "clear": us(np.median(s[:, 1] - s[:, 0])),
+        "pairs_median": us(np.median(s[:, 2] - s[:, 1])),
+        "pairs_max": us((s[:, 2] - s[:, 1]).max()),
+        "wave_spread_median": us(np.median(w.max(1) - w.min(1))),
+        "all_pairs_done": us(s[:, 2].max() - t0),
+        "project_median": us(np.median(s[:, 3] - s[:, 2])),
+        "atomics_median": us(np.median(s[:, 4] - s[:, 3])),
+        "ticket_median": us(np.median(s[:, 5] - s[:, 4])),
+        "last_pairs_to_ticket": us(s[f, 5] - s[:, 2].max()),
+        "fin_project": us(s[f, 3] - s[f, 2]),
+        "fin_atomics": us(s[f, 4] - s[f, 3]),
+        "fin_ticket": us(s[f, 5] - s[f, 4]),
+        "fin_gather": us(s[f, 6] - s[f, 5]),
+        "fin_finish": us(s[f, 7] - s[f, 6]),
+        "fin_finish_cycles": float(s[f, 11] - s[f, 10]),
+        "fin_wg_pairs_end_rank": int((s[:, 2] <= s[f, 2]).sum()),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--plan", default="1:32:512:512:8:4", help="form:band:block:grid:px_per_lane:replicas[:copies]")
+    ap.add_argument("--launches", type=int, default=30)
+    ap.add_argument("--rotate", type=int, default=32)
+    ap.add_argument("--lib", default="", help="another measurement build of the library (default: libkohler_phase.so)")
+    args = ap.parse_args()
+
+    import torch
+
+    import gen
+    import paper_1707_05062_amd as K
+    from paper_1707_05062_amd import _lib
+    from paper_1707_05062_amd.build import PHASE_LIB
+
+    ctx = K.Context(0, lib_path=args.lib or PHASE_LIB)
+    lib = ctx._lib
+    lib.kohler_phase_clock_read.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
+    lib.kohler_phase_clock_read.restype = ctypes.c_int
+    keys = ("form", "band", "block", "grid", "px_per_lane", "replicas", "copies")
+    plan = dict(zip(keys, (int(x) for x in args.plan.split(":"))))
+    img = gen.cfg2_image()
+    H, W = img.shape
+    ctx.set_plan(_lib.U8, 256, 4, **plan)
+    used = ctx.get_plan(_lib.U8, H, W, 256, 4)
+    dev = torch.device("cuda", 0)
+    src = torch.from_numpy(img).to(dev)
+    bufs = [src.clone() for _ in range(args.rotate)]
+    out = ctx.alloc_outputs(256, 256)
+    slots = np.zeros(MAXWG * SLOTS, np.uint64)
+    waves = np.zeros(MAXWG * WAVES, np.uint64)
+    for i in range(10):
+        ctx.curve_async(bufs[i % len(bufs)], 256, 4, out=out)
+    torch.cuda.synchronize()
+    rows = []
+    for i in range(args.launches):
+        assert lib.kohler_phase_clock_read(None, None, 1) == 0
+        ctx.curve_async(bufs[(10 + i) % len(bufs)], 256, 4, out=out)
+        torch.cuda.synchronize()
+        assert lib.kohler_phase_clock_read(slots.ctypes.data, waves.ctypes.data, 0) == 0
+        rows.append(breakdown(slots, waves, used["grid"], used["block"] // 64))
+        print(f"launch {i}: span {rows[-1]['span']:.2f} us", file=sys.stderr, flush=True)
+    assert int(out["ints"][2]) == 0
+    med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
+    print(f"plan {used}; {args.launches} launches of the {H}x{W} u8 image (M=256, N4); "
+          "medians over launches, microseconds")
+    print("| quantity | us |\n|---|---|")
+    for k, v in med.items():
+        print(f"| {k} | {v:.2f} |")
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
