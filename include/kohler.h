@@ -159,6 +159,28 @@ int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const k
 int kohler_get_plan(kohler_ctx *ctx, int dtype, int64_t H, int64_t W, int32_t M, int32_t nbhd,
                     kohler_plan *plan);
 
+/* int64 words of accumulator scratch that kohler_curve_noalloc keeps per GPU (512 KiB). */
+#define KOHLER_NOALLOC_SCRATCH_WORDS 65536
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. The same computation and arguments as kohler_curve_async,
+ * on the current HIP device, without a context: the kernel's scratch (accumulator replicas, ticket,
+ * range flag) is a device array of the library, one per GPU, held until the process ends, and the
+ * call makes no device or host allocation.
+ *   plan     a launch plan as kohler_set_plan takes it (grid 0 = automatic), or NULL for the
+ *            default plan; the replicas are limited to what the scratch holds
+ *            (KOHLER_NOALLOC_SCRATCH_WORDS / the replica size, at least 3 for the largest M)
+ * The first call on a device looks up and zeroes that device's array; every launch leaves it zeroed.
+ * Calls on one GPU share the array: calls that overlap on the device race, so order them on one
+ * stream. Returns KOHLER_OK, KOHLER_E_ARG (checked on the host; also an invalid plan) or
+ * KOHLER_E_DEVICE; the device writes the status as for kohler_curve_async.
+ */
+int kohler_curve_noalloc(const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch, int32_t M,
+                         int32_t nbhd, int64_t *d_sum, int64_t *d_count, double *d_C, int32_t *d_thr,
+                         int32_t thr_capacity, int32_t *d_n_thr, int32_t *d_t0, int32_t *d_status,
+                         const kohler_plan *plan, kohler_stream_t stream);
+
 /*
  * Autotuner. Times candidate plans for the (dtype, M, nbhd) family on a representative workload
  * and stores the fastest in the context, as kohler_set_plan would. The workload is described as in

@@ -20,8 +20,8 @@ from . import _lib
 from ._lib import (E_ARG, E_BUSY, E_CANCELED, E_CAPACITY, E_DEVICE, E_NOMEM, E_RANGE, OK,  # noqa: F401
                    Plan, RequestInfo, ServerConfig, ServerCounters)
 
-__all__ = ["Context", "CurveResult", "KohlerError", "Plan", "Server", "curve", "default_context",
-           "strerror"]
+__all__ = ["Context", "CurveResult", "KohlerError", "Plan", "Server", "curve", "curve_noalloc",
+           "default_context", "strerror"]
 
 FORM_AUTO, FORM_BAND, FORM_MARG, FORM_TRI = 0, 1, 2, 3
 
@@ -418,3 +418,32 @@ def default_context(device: int = 0) -> Context:
 def curve(img, M: int, nbhd: int = 4, capacity: int | None = None) -> CurveResult:
     """Synchronous curve of one image on the default context of device 0."""
     return default_context(0).curve(img, M, nbhd, capacity)
+
+
+def curve_noalloc(img, M: int, nbhd: int = 4, capacity: int | None = None, out=None, stream=None,
+                  plan: dict | None = None):
+    """Enqueue the curve of a device image through kohler_curve_noalloc, the entry point that
+    allocates nothing (its scratch is the library's per-GPU device array). `out` is a dict as
+    Context.alloc_outputs returns it (the caller allocates outputs beforehand when it cannot
+    allocate later); `plan` a dict of kohler_plan fields or None for the default plan."""
+    torch = _torch()
+    lib = _lib.load()
+    ptr, code, H, W, pitch, keep = _image_args(img)
+    cap = M if capacity is None else int(capacity)
+    if out is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
+        out = dict(sum=torch.zeros(M, dtype=torch.int64, device=dev), count=torch.zeros(M, dtype=torch.int64, device=dev),
+                   C=torch.zeros(M, dtype=torch.float64, device=dev),
+                   thr=torch.zeros(max(cap, 1), dtype=torch.int32, device=dev),
+                   ints=torch.zeros(3, dtype=torch.int32, device=dev))
+    s = stream if stream is not None else torch.cuda.current_stream()
+    pl = None if plan is None else ctypes.byref(Plan(*[int(plan.get(k, 0)) for k, _ in Plan._fields_]))
+    base = out["ints"].data_ptr()
+    st = lib.kohler_curve_noalloc(ctypes.c_void_p(ptr), code, H, W, pitch, M, nbhd, _ptr(out["sum"]),
+                                  _ptr(out["count"]), _ptr(out["C"]), _ptr(out["thr"]), cap,
+                                  ctypes.c_void_p(base), ctypes.c_void_p(base + 4), ctypes.c_void_p(base + 8),
+                                  pl, ctypes.c_void_p(s.cuda_stream))
+    del keep
+    if st != OK:
+        raise KohlerError(st, "kohler_curve_noalloc")
+    return out

@@ -23,7 +23,7 @@ PHASE_LIB = os.path.join(PKG, "libkohler_phase.so")
 ROOFLINE_LIB = os.path.join(PKG, "libkohler_roofline.so")
 ROOFLINE_SOURCE = "kohler_roofline.hip"
 
-SOURCES = ["kohler_kernels.hip", "kohler_api.cpp", "kohler_server.cpp", "kohler_segment.hip"]
+SOURCES = ["kohler_kernels.hip", "kohler_api.cpp", "kohler_server.cpp", "kohler_segment.hip", "kohler_noalloc.hip"]
 HEADERS = ["kohler_impl.h", "kohler_host.h"]
 
 HIPCC_FLAGS = [

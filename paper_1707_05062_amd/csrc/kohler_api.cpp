@@ -83,14 +83,18 @@ kohler_plan resolve_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, in
         const int64_t want = (total_units + waves * 4 - 1) / (waves * 4);  // >= 4 rows per wave
         pl.grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)ctx->num_cus * per_cu));
     }
-    // Every LDS counter of a workgroup is 32 bits: it counts at most w per pixel the workgroup sees
-    // (pairs per pixel, or the degree weight of the marginal form), and a workgroup sees about
-    // units / grid tile rows (plus one chunk), so half the counter range bounds the grid from below.
-    const int64_t w = pl.form == FORM_MARG ? 8 : (nbhd == 4 ? 2 : 4);
-    const int64_t min_grid = (w * 64 * pl.px_per_lane * total_units + (int64_t(1) << 31) - 1) >> 31;
-    if (pl.grid < min_grid) pl.grid = (int)std::min<int64_t>(min_grid, 65535);
+    pl.grid = std::max(pl.grid, min_grid_for(pl, nbhd, total_units));
     if (pl.replicas < 0) pl.replicas = replicas_for(pl.grid);
     return pl;
+}
+
+// Every LDS counter of a workgroup is 32 bits: it counts at most w per pixel the workgroup sees
+// (pairs per pixel, or the degree weight of the marginal form), and a workgroup sees about
+// units / grid tile rows (plus one chunk), so half the counter range bounds the grid from below.
+int min_grid_for(const kohler_plan &pl, int32_t nbhd, int64_t units) {
+    const int64_t w = pl.form == FORM_MARG ? 8 : (nbhd == 4 ? 2 : 4);
+    const int64_t g = (w * 64 * pl.px_per_lane * units + (int64_t(1) << 31) - 1) >> 31;
+    return (int)std::min<int64_t>(std::max<int64_t>(g, 1), 65535);
 }
 
 // Accumulator replicas for a launch of `grid` workgroups: about 32 workgroups per replica.

@@ -68,6 +68,8 @@ kohler_plan default_plan(int dtype, int32_t M);
 // grid and replicas filled in.
 kohler_plan resolve_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, int64_t total_units);
 int replicas_for(int grid);
+// Fewest workgroups for a launch over `units` tile rows so that no 32-bit LDS counter overflows.
+int min_grid_for(const kohler_plan &pl, int32_t nbhd, int64_t units);
 // Whether one int64 word per grey level can hold both difference arrays of this image.
 bool packable(int64_t H, int64_t W, int32_t nbhd);
 int64_t strips_of(int64_t W, int px_per_lane);
