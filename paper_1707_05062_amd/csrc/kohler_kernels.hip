@@ -39,7 +39,6 @@
 namespace kohler {
 namespace {
 
-constexpr int kChunk = 4;     // units (rows of a strip) a wave claims at a time in a batched launch
 
 // Explicit address spaces keep loads, stores and atomics on the global (not flat) and LDS paths.
 #define KOHLER_GLOBAL __attribute__((address_space(1)))
@@ -48,6 +47,10 @@ typedef KOHLER_LDS uint32_t lds_u32;
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));  // two 16-bit lanes of one VGPR (v_pk_* ops)
+
+__device__ __forceinline__ u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
 
 template <typename T>
 __device__ __forceinline__ const KOHLER_GLOBAL T *gptr(const T *p) {
@@ -67,9 +70,10 @@ enum : int32_t { ST_OK = 0, ST_RANGE = -2, ST_CAPACITY = -3, ST_LAYOUT = -5 };
 //   4 merge atomics performed, 5 ticket taken, 6 finishing workgroup: replicas gathered,
 //   7 finishing workgroup: done, 8 the hardware id register of the workgroup's first wave (compute
 //   unit, shader array, engine), 9 the id of its accelerator complex die (XCD), 10 and 11 the
-//   shader clock (cycles) at stamps 6 and 7.
+//   shader clock (cycles) at stamps 6 and 7, 12 .. 14 the shader clock at the finishing
+//   workgroup's three barriers (clock_stamp).
 #ifdef KOHLER_PHASE_CLOCK
-constexpr int kPhaseSlots = 12;
+constexpr int kPhaseSlots = 16;
 constexpr int kPhaseMaxWG = 4096;
 constexpr int kPhaseWaves = 16;
 __device__ unsigned long long g_phase[kPhaseMaxWG * kPhaseSlots];
@@ -79,6 +83,10 @@ __device__ __forceinline__ void phase_stamp(int slot) {
         gptr(g_phase)[blockIdx.x * kPhaseSlots + slot] = (unsigned long long)wall_clock64();
         if (slot == 6 || slot == 7) gptr(g_phase)[blockIdx.x * kPhaseSlots + slot + 4] = (unsigned long long)clock64();
     }
+}
+__device__ __forceinline__ void clock_stamp(int slot) {
+    if (threadIdx.x == 0 && blockIdx.x < (unsigned)kPhaseMaxWG)
+        gptr(g_phase)[blockIdx.x * kPhaseSlots + slot] = (unsigned long long)clock64();
 }
 __device__ __forceinline__ void phase_place() {
     if (threadIdx.x == 0 && blockIdx.x < (unsigned)kPhaseMaxWG) {
@@ -93,6 +101,7 @@ __device__ __forceinline__ void phase_wave_stamp() {
 }
 #else
 __device__ __forceinline__ void phase_stamp(int) {}
+__device__ __forceinline__ void clock_stamp(int) {}
 __device__ __forceinline__ void phase_place() {}
 __device__ __forceinline__ void phase_wave_stamp() {}
 #endif
@@ -301,24 +310,31 @@ __device__ __forceinline__ void slot_pixels(const RowSlot<Pix, K, PACKED> &sl, i
 // per-pair accumulators (LDS)
 
 // Joint histogram of (gap d, low value lo), rows kRowStride words apart, one LDS atomic per pair.
-// The workgroup keeps `copies` such tables of nb + 2 rows each, one after the other; lane l adds to
-// copy l % copies, so that fewer lanes of one LDS instruction land on the same counter (same-word
-// atomics of one instruction are serialised). Rows of a copy:
+// The workgroup keeps `copies` (C) such tables interleaved word by word: cell (d, lo) of copy c is word
+// (d * kRowStride + lo) * C + c, and lane l adds to copy l % C, so that fewer lanes of one LDS
+// instruction land on the same counter (same-word atomics of one instruction are serialised) and the
+// lanes of a copy spread over the banks. Rows (of every copy):
 //   row 0        gap-0 pairs (at their value) and invalid pairs outside the image (at their
 //                lane's column); never read back
 //   rows 1..nb   the joint counts of (d, lo)
 //   row nb+1     lo of the pairs with d > nb (their share of hmin)
-// Pixel values arrive multiplied by 4 (kScale), so that with lo4 = 4*lo and d4 = 4*d the LDS byte
-// address of the counter is (off4 + min(d4, 4*(nb+1))) * kRowStride + lo4, where off4 = 4 * the
-// first row of the lane's copy. The offset rides in the accumulator operand of the absolute
-// difference (sad), so a pair costs min, sad, min and one multiply-add whatever the copy (the table
-// starts at LDS address 0).
+// Pixel values arrive multiplied by 4 (kScale); with lo4 = 4*lo and d4 = 4*d a pair costs min, sad,
+// min and two multiply-adds: the cell's byte address 4 (d S + lo) = min(d4, 4 (nb+1)) S + lo4, times
+// C plus 4c (the table starts at LDS address 0).
 // Pairs with d > nb still owe hmax and hsum; dmax tracks the lane's largest gap so that a
 // wave-uniform test after each row can run SpillAcc over that row only when some lane needs it.
 struct BandAcc {
-    uint32_t off4;  // 4 * first row of this lane's copy
-    uint32_t cap4;  // 4 * the large-gap row of this lane's copy: off4 + 4 * (nb + 1)
-    uint32_t dmax;  // largest off4 + 4*d seen since the last test
+    uint32_t cap4;  // 4 * (nb + 1): the large-gap row
+    uint32_t nc;    // C, copies of the table
+    uint32_t off4;  // 4 * this lane's copy
+    uint32_t dmax;  // largest 4*d seen since the last test
+    // Packed form (band_row_packed): pixel values sit in 16-bit halves as C x + c, so that min gives
+    // C lo + c and max - min gives C d.
+    u16x2 mul2;     // [C, C]
+    u16x2 coff;     // [c, c]
+    u16x2 nfix;     // [0, c - c'] (mod 2^16): re-bases a value taken from the next lane (copy c')
+    u16x2 cap2;     // [C (nb + 1), C (nb + 1)]
+    u16x2 dmax2;    // largest C d seen since the last test, per half
     static constexpr uint32_t kScale = 4;
     __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
         if (!valid) {
@@ -327,18 +343,79 @@ struct BandAcc {
             x4 = y4 = 4u * (threadIdx.x & 63u);
         }
         const uint32_t lo4 = min(x4, y4);
-        const uint32_t d4 = __builtin_amdgcn_sad_u16(x4, y4, off4);  // off4 + |x4 - y4| (both below 2^16)
+        const uint32_t d4 = __builtin_amdgcn_sad_u16(x4, y4, 0u);  // |x4 - y4| (both below 2^16)
         dmax = max(dmax, d4);
-        const uint32_t row4 = min(d4, cap4);
-        lds_inc(lds_at(__umul24(row4, (uint32_t)kRowStride) + lo4));
+        const uint32_t cell4 = __umul24(min(d4, cap4), (uint32_t)kRowStride) + lo4;
+        lds_inc(lds_at(__umul24(cell4, nc) + off4));
     }
     __device__ __forceinline__ bool needs_spill() const { return dmax >= cap4; }
+    // Two pairs at once: (x.lo, y.lo) and (x.hi, y.hi), values as C x + c (see mul2); the counter of a
+    // pair is word min(C d, C (nb + 1)) * kRowStride + C lo + c, formed in the 16-bit halves (every
+    // word of the tables lies below 2^16) and shifted to a byte address per half.
+    __device__ __forceinline__ void pairs2(u16x2 x, u16x2 y) {
+        const u16x2 lo = __builtin_elementwise_min(x, y);
+        const u16x2 d = __builtin_elementwise_max(x, y) - lo;
+        dmax2 = __builtin_elementwise_max(dmax2, d);
+        const u16x2 w = __builtin_elementwise_min(d, cap2) * (uint16_t)kRowStride + lo;
+        // each half times 4 is one shift with a 16-bit source selection (SDWA)
+        lds_inc(lds_at((uint32_t)w.x * 4u));
+        lds_inc(lds_at((uint32_t)w.y * 4u));
+    }
+    __device__ __forceinline__ bool needs_spill2() const {
+        return max((uint32_t)dmax2.x, (uint32_t)dmax2.y) >= (uint32_t)cap2.x;
+    }
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
     static constexpr bool kPixels = false;
     static constexpr bool kSpill = true;
     typedef uint32_t P;
     __device__ static __forceinline__ P prep(uint32_t v) { return v; }
 };
+
+// The 8 pixels of one lane's row (two packed words of bytes) as four 16-bit pairs, each half
+// mapped to C x + c: a0 = [b0, b2], b0 = [b1, b3], a1 = [b4, b6], b1 = [b5, b7].
+struct RowPk {
+    u16x2 a0, b0, a1, b1;
+};
+
+// v_perm_b32 selectors (byte k of the result = source byte s_k; 0x0c gives zero; the second operand
+// is bytes 0..3, the first 4..7).
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_perm(hi, lo, sel);
+}
+constexpr uint32_t kSelEven = 0x0c020c00u;  // [byte 0, byte 2] as two 16-bit halves
+constexpr uint32_t kSelOdd = 0x0c030c01u;   // [byte 1, byte 3]
+constexpr uint32_t kSelHiLo = 0x05040302u;  // [high half of the second operand, low half of the first]
+
+__device__ __forceinline__ RowPk row_pk(uint32_t w0, uint32_t w1, u16x2 mul, u16x2 coff) {
+    RowPk r;
+    r.a0 = as_u16x2(perm(0u, w0, kSelEven)) * mul + coff;
+    r.b0 = as_u16x2(perm(0u, w0, kSelOdd)) * mul + coff;
+    r.a1 = as_u16x2(perm(0u, w1, kSelEven)) * mul + coff;
+    r.b1 = as_u16x2(perm(0u, w1, kSelOdd)) * mul + coff;
+    return r;
+}
+
+// The 16 pairs of one lane's row of a full 8-bit strip in the banded form, two per instruction:
+// horizontal (b0,b1)(b2,b3) | (b4,b5)(b6,b7) | (b1,b2)(b3,b4) | (b5,b6)(b7,b8), with b8 the next
+// lane's b0 (lane 63: `edge`, the edge pixel times C, as copy 0 maps it), and when there is a row
+// below, vertical (bk, bk') for k = 0..7.
+__device__ __forceinline__ void band_row_packed(const RowPk &r, const RowPk &n, uint32_t edge, bool has_down,
+                                                BandAcc &acc) {
+    acc.pairs2(r.a0, r.b0);
+    acc.pairs2(r.a1, r.b1);
+    const u16x2 c0 = as_u16x2(perm(as_u32(r.a1), as_u32(r.a0), kSelHiLo));  // [b2, b4]
+    acc.pairs2(r.b0, c0);
+    // [b6, b8]: b8 from the next lane (its copy's rebasing, corrected by nfix)
+    const uint32_t na0 = from_next_lane(as_u32(r.a0), edge);
+    const u16x2 c1 = as_u16x2(perm(na0, as_u32(r.a1), kSelHiLo)) + acc.nfix;
+    acc.pairs2(r.b1, c1);
+    if (has_down) {
+        acc.pairs2(r.a0, n.a0);
+        acc.pairs2(r.b0, n.b0);
+        acc.pairs2(r.a1, n.a1);
+        acc.pairs2(r.b1, n.b1);
+    }
+}
 
 // Triangular joint histogram of (hi, lo) with lo <= hi, for M <= 256: one LDS atomic per pair and no
 // large-gap path. Row hi starts at word T(hi) = hi (hi + 1) / 2, so the counter of a pair sits at
@@ -519,6 +596,33 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
         // row rb + j has a row below when j < down, one above when j > 0 or rb > 0 (wave-uniform)
         const int down = (int)min<int64_t>(B, H - 1 - rb);
         const bool top = rb == 0;
+        // full, aligned strips of 8-bit pixels, 8 per lane, in the banded form: two pairs per
+        // instruction (band_row_packed); rows with a large gap add its marginals in the scalar pass
+        constexpr bool kPk = std::is_same<Acc, BandAcc>::value && std::is_same<Pix, uint8_t>::value && K == 8 &&
+                             NB == 4 && FULL && PACKED;
+        if constexpr (kPk) {
+            RowPk pc = row_pk(ring[0].v[0], ring[0].v[1], acc.mul2, acc.coff);
+#pragma unroll
+            for (int j = 0; j < B; ++j) {
+                if (j < nr) {
+                    const RowPk pn = row_pk(ring[j + 1].v[0], ring[j + 1].v[1], acc.mul2, acc.coff);
+                    const uint32_t er0 = (uint32_t)__builtin_amdgcn_readlane((int)erv, j);
+                    const bool has_down = j < down;
+                    band_row_packed(pc, pn, er0 * acc.nc, has_down, acc);
+                    if (__any(acc.needs_spill2())) {
+                        uint32_t cur[K], nxt[K];
+                        slot_pixels<Pix, K, FULL, PACKED, 4>(ring[j], c, W, cur);
+                        slot_pixels<Pix, K, FULL, PACKED, 4>(ring[j + 1], c, W, nxt);
+                        const uint32_t er1 = (uint32_t)__builtin_amdgcn_readlane((int)erv, j + 1);
+                        row_pairs<NB, K, FULL>(cur, nxt, 4u * er0, 4u * er1, 0u, j > 0 || !top, has_down, c, W,
+                                               spill);
+                    }
+                    acc.dmax2 = u16x2{0, 0};
+                    pc = pn;
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             if (j < nr) {
@@ -642,74 +746,97 @@ __device__ __forceinline__ uint32_t lds_sum(const lds_u32 *tab, int i0, int i1, 
     return acc;
 }
 
-// Sum of n LDS words STEP words apart starting at q. n must be the same for every lane of the wave
-// (a per-lane trip count makes the compiler wait for each load before the next): eight loads are
-// issued, then added, and every load of an unrolled group is one instruction with an immediate
-// offset (STEP is a compile-time stride).
-template <int STEP>
-__device__ __forceinline__ uint32_t lds_column(const lds_u32 *q, int n) {
+// The C words of one cell of the banded table, loaded at once (16 bytes for four copies).
+template <int C>
+struct CellVec;
+template <>
+struct CellVec<1> {
+    typedef uint32_t T;
+    __device__ static __forceinline__ uint32_t sum(T v) { return v; }
+};
+template <>
+struct CellVec<2> {
+    typedef u32x2 T;
+    __device__ static __forceinline__ uint32_t sum(T v) { return v.x + v.y; }
+};
+template <>
+struct CellVec<4> {
+    typedef u32x4 T;
+    __device__ static __forceinline__ uint32_t sum(T v) { return (v.x + v.y) + (v.z + v.w); }
+};
+
+// Sum over all copies of n cells STEP cells apart, starting at cell `first` of the banded table (C
+// copies interleaved). n must be the same for every lane of the wave (a per-lane trip count makes
+// the compiler wait for each load before the next): eight loads are issued, then added, and each
+// is one instruction with an immediate offset (STEP is a compile-time stride).
+template <int STEP, int C>
+__device__ __forceinline__ uint32_t lds_cells(const lds_u32 *tab, int first, int n) {
+    typedef typename CellVec<C>::T V;
+    const KOHLER_LDS V *q = reinterpret_cast<const KOHLER_LDS V *>(tab) + first;
     uint32_t acc = 0;
     int k = 0;
     for (; k + 8 <= n; k += 8, q += 8 * STEP) {
-        uint32_t t[8];
+        V t[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) t[j] = q[j * STEP];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) acc += t[j];
+        for (int j = 0; j < 8; ++j) acc += CellVec<C>::sum(t[j]);
     }
-    for (; k < n; ++k, q += STEP) acc += q[0];
+    for (; k < n; ++k, q += STEP) acc += CellVec<C>::sum(q[0]);
     return acc;
 }
 
 // Projects the banded tables (all copies) on the three marginals and adds the workgroup's D1 and E
-// to the image's accumulators. With S = kRowStride, cell (d, lo) of copy c is word (c (nb+2) + d) S + lo:
+// to the image's accumulators. With S = kRowStride, cell (d, lo) is cell index d S + lo (its C copies
+// are the words C (d S + lo) .. C (d S + lo) + C - 1):
 //   hmin[v] = sum over d = 1..nb+1 of cell (d, v)   (row nb+1: the low values of the large gaps)
 //   hmax[v] = sum over d = 1..nb of cell (d, v - d), plus the large gaps' own hmax
 //   hsum[s] = sum over d = 1..nb with d = s (mod 2) of cell (d, (s - d) / 2), plus theirs
-// Column v of hmin and the diagonals of hmax and hsum step by S, S - 1 and 2S - 1 words, with the same
+// Column v of hmin and the diagonals of hmax and hsum step by S, S - 1 and 2S - 1 cells, with the same
 // number of terms for every level: a cell (d, lo) with lo + d > 255 is never written (no pair has
-// it), and neither is a row's word 256 .. S - 1, so the terms with d > v (hmax) or d > s (hsum), which
-// land there ((d, v - d) is word (d - 1) S + (S + v - d) of the row above), add zeros. Results
-// overwrite copy 0's large-gap row (hmin) and the large-gap tables (hmax, hsum): each of those words
-// is read only by the task that writes it.
-__device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, int64_t *acc) {
-    const int M = p.M, nb = p.band, nc = p.copies;
+// it), and neither is a row's cell 256 .. S - 1, so the terms with d > v (hmax) or d > s (hsum), which
+// land there ((d, v - d) is cell (d - 1) S + (S + v - d) of the row above), add zeros. hmin is written
+// over the first word of its large-gap cell, hmax and hsum over the large-gap tables: each of those
+// words is read only by the task that writes it.
+template <int C>
+__device__ __forceinline__ uint64_t merge_band_c(const KParams &p, lds_u32 *lds, int64_t *acc) {
+    const int M = p.M, nb = p.band;
     constexpr int S = kRowStride;
-    const int cwords = (nb + 2) * S;  // words per copy
-    lds_u32 *tab = lds, *lospill = lds + (nb + 1) * S, *smax = lds + nc * cwords, *ssum = smax + 256;
+    lds_u32 *tab = lds, *smax = lds + C * (nb + 2) * S, *ssum = smax + 256;
+    const int gap_row = (nb + 1) * S;  // first cell of the large-gap row
     for (int x = threadIdx.x; x < 4 * M - 1; x += blockDim.x) {
         if (x < M) {
             const int v = x;
-            uint32_t h = 0;
-            for (int c = 0; c < nc; ++c) h += lds_column<S>(tab + c * cwords + S + v, nb + 1);
-            lospill[v] = h;
+            const uint32_t h = lds_cells<S, C>(tab, S + v, nb + 1);
+            tab[(gap_row + v) * C] = h;
         } else if (x < 2 * M) {
             const int v = x - M;
-            uint32_t h = smax[v];
-            for (int c = 0; c < nc; ++c) h += lds_column<S - 1>(tab + c * cwords + S + v - 1, nb);
-            smax[v] = h;
+            smax[v] += lds_cells<S - 1, C>(tab, S + v - 1, nb);
         } else {
             const int sv = x - 2 * M;
             const int d0 = 2 - (sv & 1);  // the smallest gap with the parity of sv
-            const int base = d0 * S + (sv - d0) / 2;
-            uint32_t h = ssum[sv];
-            for (int c = 0; c < nc; ++c) {
-                // nb / 2 terms for either parity, and for an odd band one more (d = nb) for odd s
-                h += lds_column<2 * S - 1>(tab + c * cwords + base, nb / 2);
-                if ((nb & 1) && (sv & 1)) h += tab[c * cwords + nb * S + (sv - nb) / 2];
-            }
-            ssum[sv] = h;
+            // nb / 2 terms for either parity, and for an odd band one more (d = nb) for odd s
+            uint32_t h = lds_cells<2 * S - 1, C>(tab, d0 * S + (sv - d0) / 2, nb / 2);
+            if ((nb & 1) && (sv & 1)) h += lds_cells<1, C>(tab, nb * S + (sv - nb) / 2, 1);
+            ssum[sv] += h;
         }
     }
     __syncthreads();
     phase_stamp(3);
     uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
-        const int64_t d1 = (int64_t)lospill[v] - (int64_t)smax[v];
-        const int64_t e = v >= 1 ? second_diff((int64_t)lospill[v - 1] + smax[v - 1], ssum, v, M) : 0;
+        const int64_t hmin = tab[(gap_row + v) * C], hmin1 = v >= 1 ? (int64_t)tab[(gap_row + v - 1) * C] : 0;
+        const int64_t d1 = hmin - (int64_t)smax[v];
+        const int64_t e = v >= 1 ? second_diff(hmin1 + smax[v - 1], ssum, v, M) : 0;
         sink ^= add_levels(acc, M, p.packed_acc != 0, v, d1, e);
     }
     return sink;
+}
+
+__device__ __forceinline__ uint64_t merge_band(const KParams &p, lds_u32 *lds, int64_t *acc) {
+    if (p.copies == 4) return merge_band_c<4>(p, lds, acc);
+    if (p.copies == 2) return merge_band_c<2>(p, lds, acc);
+    return merge_band_c<1>(p, lds, acc);
 }
 
 // Project the triangular table onto hmax (row sums without the diagonal), hmin (column sums below
@@ -916,6 +1043,7 @@ __device__ __forceinline__ void finalize_small(const KParams &p, int i, lds_u32 
         fs.tot[w][2] = x2;
     }
     __syncthreads();
+    clock_stamp(12);
     int64_t c0 = 0, c1 = 0, c2 = 0;  // totals of the waves before this one
     for (int v = 0; v < w && v < kFinWaves; ++v) {
         c0 += fs.tot[v][0];
@@ -953,6 +1081,7 @@ __device__ __forceinline__ void finalize_small(const KParams &p, int i, lds_u32 
         fs.cnt[t] = cnt;
     }
     __syncthreads();
+    clock_stamp(13);
 
     // 4. local maxima: the first change after t, in this wave or in a later one
     int next = -1;  // 1: fall, 0: rise, -1: no change before M
@@ -979,6 +1108,7 @@ __device__ __forceinline__ void finalize_small(const KParams &p, int i, lds_u32 
         fs.cand[w] = CA;
     }
     __syncthreads();
+    clock_stamp(14);
 
     // 5. compaction of the maxima in ascending order, and t0
     uint32_t below = 0, found = 0, ncand = 0;
@@ -1293,8 +1423,11 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
         uint32_t vmax = 0;
         if constexpr (FORM == FORM_BAND) {
             const uint32_t nb = (uint32_t)p.band, rows = nb + 2u;
-            const uint32_t off4 = 4u * rows * ((threadIdx.x & 63u) % (uint32_t)p.copies);
-            BandAcc acc{off4, off4 + 4u * (nb + 1u), 0u};
+            const uint32_t lane = threadIdx.x & 63u, nc = (uint32_t)p.copies;
+            const uint32_t cl = lane % nc, cn = ((lane + 1u) & 63u) % nc;  // copies of this lane and the next
+            const uint16_t C16 = (uint16_t)nc, cap = (uint16_t)(nc * (nb + 1u));
+            BandAcc acc{4u * (nb + 1u), nc, 4u * cl, 0u, u16x2{C16, C16}, u16x2{(uint16_t)cl, (uint16_t)cl},
+                        u16x2{0, (uint16_t)(cl - cn)}, u16x2{cap, cap}, u16x2{0, 0}};
             const uint32_t spill0 = 4u * (uint32_t)p.copies * rows * kRowStride;
             SpillAcc spill{spill0, spill0 + 4u * 256u, nb};
             chunks(acc, spill, vmax, Mm1 * BandAcc::kScale);
@@ -1354,29 +1487,64 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
         __syncthreads();
     };
 
+    // rows a wave processes at a time: a chunk of the single-image launch, a claim of the batched one
+    constexpr int B = row_batch<Pix, NB, K, CLAMP>();
+    auto nothing = []() {};
+
     if (p.dyn) {
-        // One image, static work: the launch's Q waves split the image's units (rows of strips,
-        // strip-major) into Q contiguous ranges, and wave w of logical workgroup g takes range
-        // w * G + g. The ranges of one workgroup (and of one SIMD) lie far apart in the image, so
-        // costly regions (many large-gap pairs) spread over the compute units. The tables are
-        // cleared first: a barrier after the first loads would wait until every wave has issued
-        // them, which the opening burst of requests throttles. The ticket counts waves.
+        // One image: a chunk is B consecutive rows of one strip. Chunks are numbered row-block major
+        // (chunk c covers strip c mod nstrips of row block c / nstrips), so neighbouring strips of
+        // the same rows get consecutive numbers, and they are dealt round-robin to the workgroups
+        // (chunk c to logical workgroup c mod G): every workgroup samples the whole image, costly
+        // regions (many large-gap pairs) spread evenly, and the next strip's first column, which a
+        // strip's rows also read, is fetched at about the same time by a workgroup on the same XCD
+        // (shared L2). Waves claim their workgroup's chunks in turn, the last ones in half-chunk
+        // pieces so that the waves finish closer together.
         const KImage im = image_desc(p, 0);
-        const int nw = (int)(blockDim.x >> 6);
-        const int w = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int64_t Q = (int64_t)G * nw, q = (int64_t)w * G + g;
-        const int64_t ua = q * im.nunits / Q, ub = (q + 1) * im.nunits / Q;
+        const int64_t ns = im.nstrips;
+        const int64_t nblocks = (im.H + B - 1) / B;
+        const int64_t nchunks = nblocks * ns;
+        // number of chunks c < n with c = g (mod G)
+        auto upto = [&](int64_t n) -> int64_t { return n > g ? (n - g - 1) / G + 1 : 0; };
+        const int64_t mine = upto(nchunks);  // chunks of this workgroup
         clear_tables();
-        auto nothing = []() {};
+        auto claim = [&]() -> uint32_t {
+            uint32_t k = 0;
+            if ((threadIdx.x & 63) == 0)
+                k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return (uint32_t)__builtin_amdgcn_readfirstlane(k);
+        };
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
-            wave_units<Pix, NB, K, CLAMP>(im, ua, ub, mm1, acc, spill, vm, nothing);
+            // chunk numbers stay below 2^32 (at most 2^40 pixels, chunks of B >= 4 rows by at least
+            // 256 columns), so the decode is a 32-bit division by a wave-uniform value
+            constexpr uint32_t kHalf = (uint32_t)B / 2, kPieces = 2;
+            const uint32_t ntail = (uint32_t)min<int64_t>(mine, (int64_t)(blockDim.x >> 7));
+            const uint32_t whole = (uint32_t)mine - ntail;
+            const uint32_t nclaims = whole + ntail * kPieces;
+            for (uint32_t j = claim(); j < nclaims; j = claim()) {
+                uint32_t jc = j, off = 0, len = (uint32_t)B;
+                if (j >= whole) {
+                    jc = whole + (j - whole) / kPieces;
+                    off = ((j - whole) % kPieces) * kHalf;
+                    len = off ? (uint32_t)B - kHalf : kHalf;
+                }
+                const uint32_t c = (uint32_t)g + jc * (uint32_t)G;
+                const uint32_t blk = c / (uint32_t)ns, strip = c - blk * (uint32_t)ns;
+                const int64_t r0 = (int64_t)blk * B + off;
+                if (r0 < im.H)  // a piece past the last row of a short final row block is empty
+                    strip_range<Pix, NB, K, CLAMP>(im, (int)strip, r0, min(im.H, r0 + (int64_t)len), mm1, acc,
+                                                   spill, vm, nothing);
+            }
         });
-        flush(im, vmax, nw, Q);
+        // units of this workgroup: B rows per chunk, less the short chunks of the last row block
+        const int64_t last_rows = im.H - (nblocks - 1) * B;
+        const int64_t units = mine * B - (upto(nchunks) - upto(nchunks - ns)) * (B - last_rows);
+        flush(im, vmax, units, im.nunits);
         return;
     }
 
     // Several images: each workgroup takes a contiguous range of the launch's unit space; inside an
-    // image's part of it, waves claim chunks of kChunk units from a workgroup counter.
+    // image's part of it, waves claim chunks of B units from a workgroup counter.
     const int64_t U = p.total_units;
     int64_t u = (int64_t)g * U / G;
     const int64_t uend = (int64_t)(g + 1) * U / G;
@@ -1387,17 +1555,16 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
         const int64_t nseg = seg_end - u;
         clear_tables();
         const int64_t lbase = u - im.ustart;
-        const uint32_t nchunks = (uint32_t)((nseg + kChunk - 1) / kChunk);
+        const uint32_t nchunks = (uint32_t)((nseg + B - 1) / B);
         auto claim = [&]() -> uint32_t {
             uint32_t k = 0;
             if ((threadIdx.x & 63) == 0)
                 k = __hip_atomic_fetch_add(&bs.next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return (uint32_t)__builtin_amdgcn_readfirstlane(k);
         };
-        auto nothing = []() {};
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
             for (uint32_t k = claim(); k < nchunks; k = claim()) {
-                const int64_t ca = lbase + (int64_t)k * kChunk, cb = min(lbase + nseg, ca + kChunk);
+                const int64_t ca = lbase + (int64_t)k * B, cb = min(lbase + nseg, ca + B);
                 wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm, nothing);
             }
         });

@@ -21,7 +21,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-SLOTS, MAXWG, WAVES = 12, 4096, 16
+SLOTS, MAXWG, WAVES = 16, 4096, 16
 TICK_US = 0.01  # the real-time counter runs at 100 MHz
 
 
@@ -57,6 +57,10 @@ def breakdown(slots: np.ndarray, waves: np.ndarray, grid: int, nwaves: int) -> d
         "fin_gather": us(s[f, 6] - s[f, 5]),
         "fin_finish": us(s[f, 7] - s[f, 6]),
         "fin_finish_cycles": float(s[f, 11] - s[f, 10]),
+        "fin_cycles_scan": float(s[f, 12] - s[f, 10]),
+        "fin_cycles_compare": float(s[f, 13] - s[f, 12]),
+        "fin_cycles_maxima": float(s[f, 14] - s[f, 13]),
+        "fin_cycles_out": float(s[f, 11] - s[f, 14]),
         "fin_wg_pairs_end_rank": int((s[:, 2] <= s[f, 2]).sum()),
     }
 
