@@ -328,7 +328,7 @@ struct BandAcc {
     uint32_t nc;    // C, copies of the table
     uint32_t off4;  // 4 * this lane's copy
     uint32_t dmax;  // largest 4*d seen since the last test
-    // Packed form (band_row_packed): pixel values sit in 16-bit halves as C x + c, so that min gives
+    // Packed form (band_row_pairs): pixel values sit in 16-bit halves as C x + c, so that min gives
     // C lo + c and max - min gives C d.
     u16x2 mul2;     // [C, C]
     u16x2 coff;     // [c, c]
@@ -395,25 +395,26 @@ __device__ __forceinline__ RowPk row_pk(uint32_t w0, uint32_t w1, u16x2 mul, u16
     return r;
 }
 
-// The 16 pairs of one lane's row of a full 8-bit strip in the banded form, two per instruction:
+// The 16 pairs of one lane's row of a full 8-bit strip in the banded form, two per call of f:
 // horizontal (b0,b1)(b2,b3) | (b4,b5)(b6,b7) | (b1,b2)(b3,b4) | (b5,b6)(b7,b8), with b8 the next
 // lane's b0 (lane 63: `edge`, the edge pixel times C, as copy 0 maps it), and when there is a row
-// below, vertical (bk, bk') for k = 0..7.
-__device__ __forceinline__ void band_row_packed(const RowPk &r, const RowPk &n, uint32_t edge, bool has_down,
-                                                BandAcc &acc) {
-    acc.pairs2(r.a0, r.b0);
-    acc.pairs2(r.a1, r.b1);
+// below, vertical (bk, bk') for k = 0..7. Both values of a pair carry this lane's copy offset.
+template <class F>
+__device__ __forceinline__ void band_row_pairs(const RowPk &r, const RowPk &n, uint32_t edge, bool has_down,
+                                               u16x2 nfix, F &&f) {
+    f(r.a0, r.b0);
+    f(r.a1, r.b1);
     const u16x2 c0 = as_u16x2(perm(as_u32(r.a1), as_u32(r.a0), kSelHiLo));  // [b2, b4]
-    acc.pairs2(r.b0, c0);
+    f(r.b0, c0);
     // [b6, b8]: b8 from the next lane (its copy's rebasing, corrected by nfix)
     const uint32_t na0 = from_next_lane(as_u32(r.a0), edge);
-    const u16x2 c1 = as_u16x2(perm(na0, as_u32(r.a1), kSelHiLo)) + acc.nfix;
-    acc.pairs2(r.b1, c1);
+    const u16x2 c1 = as_u16x2(perm(na0, as_u32(r.a1), kSelHiLo)) + nfix;
+    f(r.b1, c1);
     if (has_down) {
-        acc.pairs2(r.a0, n.a0);
-        acc.pairs2(r.b0, n.b0);
-        acc.pairs2(r.a1, n.a1);
-        acc.pairs2(r.b1, n.b1);
+        f(r.a0, n.a0);
+        f(r.b0, n.b0);
+        f(r.a1, n.a1);
+        f(r.b1, n.b1);
     }
 }
 
@@ -548,16 +549,132 @@ constexpr int row_batch() {
     return (K * (int)sizeof(Pix)) / 4 <= 1 ? ((CLAMP || NB == 8) ? 12 : 16) : ((CLAMP || NB == 8) ? 4 : 6);
 }
 
-// Rows [r0, r1) of strip s, by one wave, in batches of row_batch() rows: a batch issues the loads of
+// Rows of one batch of strip_rows: row_batch(), but 3 where a slot holds 8 unpacked pixels (element
+// loads: ragged last strips and misaligned rows), whose ring of 8-word slots would not fit otherwise.
+template <typename Pix, int NB, int K, bool CLAMP, bool PACKED>
+constexpr int slot_batch() {
+    return (!PACKED && K >= 8) ? 3 : row_batch<Pix, NB, K, CLAMP>();
+}
+
+// ------------------------------------------------------------------------------------------------
+// Full, aligned strips of 8-bit pixels (8 per lane, 4-neighbourhood, banded form, no clamping):
+// batches of kPkRows rows, software-pipelined (the loads of the next batch are in flight while this
+// one is used), with the pairs formed two per instruction (band_row_pairs).
+
+#ifndef KOHLER_PK_ROWS
+#define KOHLER_PK_ROWS 6
+#endif
+constexpr int kPkRows = KOHLER_PK_ROWS;
+static_assert(kPkRows >= 1 && kPkRows < 64, "one lane per row of a batch holds its edge pixel");
+
+// Whether an instance takes this path (for the strips that lie wholly inside the image).
+template <typename Pix, int NB, int K, bool CLAMP, class Acc>
+constexpr bool pk_form() {
+    return std::is_same<Acc, BandAcc>::value && std::is_same<Pix, uint8_t>::value && K == 8 && NB == 4 && !CLAMP;
+}
+
+struct PkBatch {
+    RowSlot<uint8_t, 8, true> ring[kPkRows + 1];  // the rows and the halo row below
+    uint32_t erv;                                 // lane j: right edge pixel of row j
+    int64_t rb;                                   // first row
+    int s, nr;                                    // strip, rows in the batch
+};
+
+// Issues the loads of rows [rb, r1) (r1 - rb <= kPkRows) of strip s, which lies wholly inside the
+// image, and of the halo row below. The pixel right of the strip is read at column min((s + 1) 512,
+// W - 1): at the image's right border that is the row's last pixel, which pairs with itself (gap 0,
+// a pair that adds nothing).
+__device__ __forceinline__ void pk_load(const KImage &im, int s, int64_t rb, int64_t r1, PkBatch &b) {
+    constexpr int SW = 64 * 8;
+    const int lane = threadIdx.x & 63;
+    const uint8_t *base = static_cast<const uint8_t *>(im.ptr);
+    const int64_t pitch = im.pitch;
+    const int c = s * SW + lane * 8;
+    const int room = (int)(min(r1, im.H - 1) - rb);  // rows past the range re-read the last one
+    b.rb = rb;
+    b.s = s;
+    b.nr = (int)(r1 - rb);
+    b.erv = (uint32_t)gptr(base + (rb + min(lane, room)) * pitch)[(uint32_t)min<int64_t>((int64_t)(s + 1) * SW, im.W - 1)];
+    const uint8_t *rowp = base + rb * pitch;
+#pragma unroll
+    for (int j = 0; j <= kPkRows; ++j) {
+        load_slot<uint8_t, 8, true, true>(rowp, c, (int)im.W, b.ring[j]);
+        if (j < room) rowp += pitch;
+    }
+}
+
+// The pairs of a loaded batch. A row with a pair of gap > nb runs the pairs again for the large-gap
+// tables: with values v stored as C v + c (C a power of two <= 4), a pair (x, y) of such values has
+// gap |x - y| / C, and the byte offsets of 4 max(v) and 4 (v + v') are (max(x, y) - c) << sh and
+// (x + y - 2c) << sh with sh = 2 - log2 C.
+template <class Spill>
+__device__ __forceinline__ void pk_use(const KImage &im, const PkBatch &b, BandAcc &acc, Spill &spill) {
+    const int down = (int)min<int64_t>(kPkRows, im.H - 1 - b.rb);
+    const uint32_t c = acc.coff.x, c2 = 2u * c;
+    const uint32_t sh = acc.nc == 1u ? 2u : (acc.nc == 2u ? 1u : 0u);
+    const uint32_t cnb = acc.nc * spill.nb;
+    RowPk pc = row_pk(b.ring[0].v[0], b.ring[0].v[1], acc.mul2, acc.coff);
+#pragma unroll
+    for (int j = 0; j < kPkRows; ++j) {
+        if (j < b.nr) {
+            const RowPk pn = row_pk(b.ring[j + 1].v[0], b.ring[j + 1].v[1], acc.mul2, acc.coff);
+            const uint32_t edge = (uint32_t)__builtin_amdgcn_readlane((int)b.erv, j) * acc.nc;
+            const bool has_down = j < down;
+            band_row_pairs(pc, pn, edge, has_down, acc.nfix, [&](u16x2 x, u16x2 y) { acc.pairs2(x, y); });
+            if (__any(acc.needs_spill2())) {
+                band_row_pairs(pc, pn, edge, has_down, acc.nfix, [&](u16x2 x, u16x2 y) {
+                    const u16x2 hi = __builtin_elementwise_max(x, y), d = hi - __builtin_elementwise_min(x, y);
+                    const u16x2 t = x + y;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if ((uint32_t)d[h] > cnb) {
+                            lds_inc(lds_at(spill.smax + (((uint32_t)hi[h] - c) << sh)));
+                            lds_inc(lds_at(spill.ssum + (((uint32_t)t[h] - c2) << sh)));
+                        }
+                    }
+                });
+            }
+            acc.dmax2 = u16x2{0, 0};
+            pc = pn;
+        }
+    }
+}
+
+// Rows [r0, r1) of full strip s, two batches in flight.
+template <class Spill>
+__device__ __forceinline__ void pk_rows(const KImage &im, int s, int64_t r0, int64_t r1, BandAcc &acc,
+                                        Spill &spill) {
+    PkBatch ba, bb;
+    int64_t r = min(r0 + kPkRows, r1);
+    pk_load(im, s, r0, r, ba);
+    for (;;) {
+        const bool vb = r < r1;
+        if (vb) {
+            const int64_t e = min(r + kPkRows, r1);
+            pk_load(im, s, r, e, bb);
+            r = e;
+        }
+        pk_use(im, ba, acc, spill);
+        if (!vb) break;
+        const bool va = r < r1;
+        if (va) {
+            const int64_t e = min(r + kPkRows, r1);
+            pk_load(im, s, r, e, ba);
+            r = e;
+        }
+        pk_use(im, bb, acc, spill);
+        if (!va) break;
+    }
+}
+
+// Rows [r0, r1) of strip s, by one wave, in batches of slot_batch() rows: a batch issues the loads of
 // its rows and of the halo row below before it uses any of them, and uses them in order, so the
-// whole batch is in flight at once and the wait before each row only covers that row. `first` runs
-// once, after the loads of the wave's first batch are issued and before its first LDS update (the
-// single-image launch clears its tables there, so the first loads overlap the clearing).
-template <typename Pix, int NB, int K, bool CLAMP, bool FULL, bool PACKED, class Acc, class Spill, class First>
+// whole batch is in flight at once and the wait before each row only covers that row.
+template <typename Pix, int NB, int K, bool CLAMP, bool FULL, bool PACKED, class Acc, class Spill>
 __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
-                                           Acc &acc, Spill &spill, uint32_t &vmax, First &first) {
+                                           Acc &acc, Spill &spill, uint32_t &vmax) {
     constexpr int SW = 64 * K;
-    constexpr int B = row_batch<Pix, NB, K, CLAMP>();
+    constexpr int B = slot_batch<Pix, NB, K, CLAMP, PACKED>();
     const int lane = threadIdx.x & 63;
     const Pix *base = static_cast<const Pix *>(im.ptr);
     const int64_t H = im.H, pitch = im.pitch;
@@ -592,37 +709,9 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
                 if (j < room) rowp += pitch;
             }
         }
-        first();
         // row rb + j has a row below when j < down, one above when j > 0 or rb > 0 (wave-uniform)
         const int down = (int)min<int64_t>(B, H - 1 - rb);
         const bool top = rb == 0;
-        // full, aligned strips of 8-bit pixels, 8 per lane, in the banded form: two pairs per
-        // instruction (band_row_packed); rows with a large gap add its marginals in the scalar pass
-        constexpr bool kPk = std::is_same<Acc, BandAcc>::value && std::is_same<Pix, uint8_t>::value && K == 8 &&
-                             NB == 4 && FULL && PACKED;
-        if constexpr (kPk) {
-            RowPk pc = row_pk(ring[0].v[0], ring[0].v[1], acc.mul2, acc.coff);
-#pragma unroll
-            for (int j = 0; j < B; ++j) {
-                if (j < nr) {
-                    const RowPk pn = row_pk(ring[j + 1].v[0], ring[j + 1].v[1], acc.mul2, acc.coff);
-                    const uint32_t er0 = (uint32_t)__builtin_amdgcn_readlane((int)erv, j);
-                    const bool has_down = j < down;
-                    band_row_packed(pc, pn, er0 * acc.nc, has_down, acc);
-                    if (__any(acc.needs_spill2())) {
-                        uint32_t cur[K], nxt[K];
-                        slot_pixels<Pix, K, FULL, PACKED, 4>(ring[j], c, W, cur);
-                        slot_pixels<Pix, K, FULL, PACKED, 4>(ring[j + 1], c, W, nxt);
-                        const uint32_t er1 = (uint32_t)__builtin_amdgcn_readlane((int)erv, j + 1);
-                        row_pairs<NB, K, FULL>(cur, nxt, 4u * er0, 4u * er1, 0u, j > 0 || !top, has_down, c, W,
-                                               spill);
-                    }
-                    acc.dmax2 = u16x2{0, 0};
-                    pc = pn;
-                }
-            }
-            continue;
-        }
 #pragma unroll
         for (int j = 0; j < B; ++j) {
             if (j < nr) {
@@ -670,32 +759,38 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
 }
 
 // Rows [r0, r1) of strip s of one image, by one wave.
-template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill, class First>
+template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
 __device__ __forceinline__ void strip_range(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
-                                            Acc &acc, Spill &spill, uint32_t &vmax, First &first) {
+                                            Acc &acc, Spill &spill, uint32_t &vmax) {
     constexpr int SW = 64 * K;
+    if constexpr (pk_form<Pix, NB, K, CLAMP, Acc>()) {
+        if (im.vec_ok && (int64_t)(s + 1) * SW <= im.W) {
+            pk_rows(im, s, r0, r1, acc, spill);
+            return;
+        }
+    }
     if ((int64_t)(s + 1) * SW < im.W) {
         if (im.vec_ok)
-            strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
+            strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
         else
-            strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
+            strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
     } else if (im.vec_ok && im.W % K == 0) {
-        strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
+        strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
     } else {
-        strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax, first);
+        strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
     }
 }
 
 // Units [la, lb) of one image (image-local, strip-major), by one wave.
-template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill, class First>
+template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
 __device__ __forceinline__ void wave_units(const KImage &im, int64_t la, int64_t lb, uint32_t Mm1, Acc &acc,
-                                           Spill &spill, uint32_t &vmax, First &first) {
+                                           Spill &spill, uint32_t &vmax) {
     int64_t u = la;
     while (u < lb) {
         const int s = (int)(u / im.H);
         const int64_t r = u - (int64_t)s * im.H;
         const int64_t rend = min(im.H, r + (lb - u));
-        strip_range<Pix, NB, K, CLAMP>(im, s, r, rend, Mm1, acc, spill, vmax, first);
+        strip_range<Pix, NB, K, CLAMP>(im, s, r, rend, Mm1, acc, spill, vmax);
         u += rend - r;
     }
 }
@@ -1489,7 +1584,6 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
 
     // rows a wave processes at a time: a chunk of the single-image launch, a claim of the batched one
     constexpr int B = row_batch<Pix, NB, K, CLAMP>();
-    auto nothing = []() {};
 
     if (p.dyn) {
         // One image: a chunk is B consecutive rows of one strip. Chunks are numbered row-block major
@@ -1521,7 +1615,9 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
             const uint32_t ntail = (uint32_t)min<int64_t>(mine, (int64_t)(blockDim.x >> 7));
             const uint32_t whole = (uint32_t)mine - ntail;
             const uint32_t nclaims = whole + ntail * kPieces;
-            for (uint32_t j = claim(); j < nclaims; j = claim()) {
+            // strip and rows [r0, r1) of claim j (empty: a piece past the last row of a short final
+            // row block)
+            auto decode = [&](uint32_t j, int &strip, int64_t &r0, int64_t &r1) {
                 uint32_t jc = j, off = 0, len = (uint32_t)B;
                 if (j >= whole) {
                     jc = whole + (j - whole) / kPieces;
@@ -1529,11 +1625,16 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
                     len = off ? (uint32_t)B - kHalf : kHalf;
                 }
                 const uint32_t c = (uint32_t)g + jc * (uint32_t)G;
-                const uint32_t blk = c / (uint32_t)ns, strip = c - blk * (uint32_t)ns;
-                const int64_t r0 = (int64_t)blk * B + off;
-                if (r0 < im.H)  // a piece past the last row of a short final row block is empty
-                    strip_range<Pix, NB, K, CLAMP>(im, (int)strip, r0, min(im.H, r0 + (int64_t)len), mm1, acc,
-                                                   spill, vm, nothing);
+                const uint32_t blk = c / (uint32_t)ns;
+                strip = (int)(c - blk * (uint32_t)ns);
+                r0 = (int64_t)blk * B + off;
+                r1 = min(im.H, r0 + (int64_t)len);
+            };
+            for (uint32_t j = claim(); j < nclaims; j = claim()) {
+                int strip;
+                int64_t r0, r1;
+                decode(j, strip, r0, r1);
+                if (r0 < r1) strip_range<Pix, NB, K, CLAMP>(im, strip, r0, r1, mm1, acc, spill, vm);
             }
         });
         // units of this workgroup: B rows per chunk, less the short chunks of the last row block
@@ -1565,7 +1666,7 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
             for (uint32_t k = claim(); k < nchunks; k = claim()) {
                 const int64_t ca = lbase + (int64_t)k * B, cb = min(lbase + nseg, ca + B);
-                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm, nothing);
+                wave_units<Pix, NB, K, CLAMP>(im, ca, cb, mm1, acc, spill, vm);
             }
         });
         flush(im, vmax, nseg, im.nunits);

@@ -130,13 +130,39 @@ def test_plan_sweep(ctx, K):
                     for ppl in (4, 8):
                         plans.append((form, band, block, grid, ppl))
         for form, band, block, grid, ppl in plans:
-            ctx.set_plan(1, 256, nbhd, form=form, band=band, block=block, grid=grid, px_per_lane=ppl)
-            res = ctx.curve(dev, 256, nbhd)
-            assert_result(res, ref, what=f"plan {form},{band},{block},{grid},{ppl} N{nbhd}")
+            for copies in ((1, 2, 4) if form == K.FORM_BAND else (0,)):
+                if copies * (band + 2) * 272 * 4 + 768 * 4 + 512 > 160 * 1024:
+                    continue  # the tables would not fit the LDS: the plan is refused
+                ctx.set_plan(1, 256, nbhd, form=form, band=band, block=block, grid=grid, px_per_lane=ppl,
+                             copies=copies)
+                res = ctx.curve(dev, 256, nbhd)
+                assert_result(res, ref, what=f"plan {form},{band},{block},{grid},{ppl},c{copies} N{nbhd}")
         say("plans checked", len(plans), "N", nbhd)
     # restore defaults for other tests
     for nbhd in (4, 8):
         ctx.set_plan(1, 256, nbhd)
+
+
+@pytest.mark.parametrize("W", [512, 520, 1024, 1100, 1536])
+def test_packed_strip_borders(ctx, K, W):
+    """8-bit pixels, 8 per lane, banded form: strips that end exactly at the right border (the edge
+    pixel is the row's own last pixel), strips that cross it, short images (fewer rows than a
+    batch or a chunk) and rows with large gaps, over table copies, workgroup sizes and grids, in
+    the single-image and the batched launch."""
+    rng = np.random.default_rng(W)
+    for H in (1, 2, 3, 4, 7, 61):
+        img = gen.random_image(rng, H, W, 256, np.uint8, "smooth")
+        img[H // 2, W // 3: W // 3 + 200] = rng.integers(0, 256, size=len(img[H // 2, W // 3: W // 3 + 200]))
+        dev = to_device(img)
+        ref = reference(img, 256, 4)
+        for copies in (1, 2, 4):
+            for block, grid in [(256, 1), (1024, 3), (1024, 0), (512, 0)]:
+                ctx.set_plan(1, 256, 4, form=K.FORM_BAND, band=32, block=block, grid=grid, px_per_lane=8,
+                             copies=copies)
+                res = ctx.curve(dev, 256, 4)
+                assert_result(res, ref, what=f"{H}x{W} c{copies} b{block} g{grid}")
+        _batch_check(ctx, [img, gen.random_image(rng, 5, 700, 256, np.uint8, "uniform"), img], 256, 4)
+    ctx.set_plan(1, 256, 4)
 
 
 # ----------------------------------------------------------------------------------------------
