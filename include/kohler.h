@@ -85,7 +85,9 @@ const char *kohler_strerror(int status);
 /*
  * Synchronous curve of one image (Sec. 2.1, eqs (1)-(4); result equal to Algorithm 1 of Sec. 3.1).
  *   img          device or host pointer to H rows of `pitch` elements of `dtype`; a host image is
- *                copied to the device through the context's staging buffer first.
+ *                copied to the device through the context's staging buffer first. The call works
+ *                on the context's own stream, which does not wait for any other stream: a device
+ *                image must be complete (every write to it finished) when the call is made.
  *   sum, count   HOST arrays of M int64 (required).
  *   C            HOST array of M doubles (required).
  *   thresholds   HOST array of thr_capacity int32 (may be NULL when thr_capacity == 0).
@@ -139,6 +141,10 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
  *   copies      LDS privatisation width of the banded form: copies of the joint table each
  *               workgroup keeps, lane l of a wave adding to copy l % copies (1, 2 or 4; 0 =
  *               automatic; other forms use 1)
+ *   acc_split   layout of the device accumulators: 0 = automatic (one int64 word per grey level
+ *               holding E * 2^32 + D1 while the image, or every image of a batched launch, has
+ *               fewer than 2^30 neighbour pairs, else two words), 1 = always two words (D1 and E
+ *               apart: the layout very large images need, selectable for any image)
  * The grid is raised where needed so that no workgroup's 32-bit LDS counter can overflow: at least
  * ceil(w * 64 * px_per_lane * units / 2^31) workgroups for a launch over `units` tile rows, with w = 2
  * (nbhd 4) or 4 (nbhd 8) pairs per pixel, 8 for the marginal form.
@@ -153,6 +159,7 @@ typedef struct kohler_plan {
     int32_t px_per_lane;
     int32_t replicas;
     int32_t copies;
+    int32_t acc_split;
 } kohler_plan;
 
 int kohler_set_plan(kohler_ctx *ctx, int dtype, int32_t M, int32_t nbhd, const kohler_plan *plan);
@@ -190,7 +197,8 @@ int kohler_curve_noalloc(const void *d_img, int dtype, int64_t H, int64_t W, int
  * unit) and replicas, starting from the default plan, then a joint sweep of band (banded form),
  * px_per_lane, grid and replicas (1, 2, 4, 8) around the result; each
  * candidate gets two warm-up launches and `reps` timed ones (0 means 5) on the context's stream,
- * and its median time counts.
+ * and its median time counts. The device images must be complete when the call is made (the
+ * context's stream does not wait for the caller's streams).
  *   best     out: the chosen plan (grid and replicas may be 0 = automatic)
  *   best_us  out (may be NULL): its median launch time in microseconds
  * It allocates and frees temporary device outputs and synchronises the context's stream, so it
@@ -344,7 +352,8 @@ void kohler_server_destroy(kohler_server *srv);
 /*
  * Submit one image (H rows of `pitch` elements of the server's dtype). A device or pinned host
  * image is read in place and must stay valid and unchanged until the request completes; a pageable
- * host image is copied into pinned staging before this returns. Returns KOHLER_OK and a ticket,
+ * host image is copied into pinned staging before this returns. The server's lanes do not wait for
+ * the caller's streams: a device image must be complete (every write to it finished) at submission. Returns KOHLER_OK and a ticket,
  * KOHLER_E_ARG (bad shape), or KOHLER_E_BUSY when the queue is full or the image alone exceeds the
  * image arena (then no ticket is issued).
  */

@@ -84,6 +84,15 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _complete(img):
+    """Entry points that work on the library's own streams (the synchronous curve, the autotuner,
+    server submission) read a device image without waiting for the caller's streams: wait here for
+    torch's current stream of the image's device, which produced it in the usual case."""
+    torch = _torch()
+    if isinstance(img, torch.Tensor) and img.is_cuda:
+        torch.cuda.current_stream(img.device).synchronize()
+
+
 class Context:
     """A library context bound to one HIP device (owns device scratch and a stream)."""
 
@@ -109,8 +118,9 @@ class Context:
 
     # -- plans -------------------------------------------------------------------------------
     def set_plan(self, dtype: int, M: int, nbhd: int, form: int = FORM_AUTO, band: int = 0,
-                 block: int = 512, grid: int = 0, px_per_lane: int = 4, replicas: int = 0, copies: int = 0):
-        pl = Plan(form, band, block, grid, px_per_lane, replicas, copies)
+                 block: int = 512, grid: int = 0, px_per_lane: int = 4, replicas: int = 0, copies: int = 0,
+                 acc_split: int = 0):
+        pl = Plan(form, band, block, grid, px_per_lane, replicas, copies, acc_split)
         st = self._lib.kohler_set_plan(self._h, dtype, M, nbhd, ctypes.byref(pl))
         if st != OK:
             raise KohlerError(st, "kohler_set_plan")
@@ -139,6 +149,7 @@ class Context:
                 raise TypeError("all images must share one dtype")
             code = c
             ptrs[i], Hs[i], Ws[i], Ps[i] = p, H, W, pitch
+            _complete(im)
         best = Plan()
         us = ctypes.c_double(0.0)
         st = self._lib.kohler_autotune(self._h, n, ptrs, Hs, Ws, Ps, code, M, nbhd, reps,
@@ -229,6 +240,7 @@ class Context:
               check: bool = True) -> CurveResult:
         """Curve of one image (device tensor or host array); results as numpy arrays."""
         ptr, code, H, W, pitch, keep = _image_args(img)
+        _complete(img)
         cap = M if capacity is None else int(capacity)
         m = max(int(M), 1)  # the library validates M; the buffers only need to exist
         s = np.zeros(m, np.int64)
@@ -358,6 +370,7 @@ class Server:
         ptr, code, H, W, pitch, keep = _image_args(img)
         if code != self.dtype:
             raise TypeError("image dtype does not match the server")
+        _complete(img)
         t = ctypes.c_uint64(0)
         st = self._lib.kohler_server_submit(self._h, ctypes.c_void_p(ptr), H, W, pitch, ctypes.byref(t))
         if st != OK:

@@ -29,7 +29,7 @@ class _Struct(ctypes.Structure):
 class Plan(_Struct):
     _fields_ = [("form", ctypes.c_int32), ("band", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("px_per_lane", ctypes.c_int32),
-                ("replicas", ctypes.c_int32), ("copies", ctypes.c_int32)]
+                ("replicas", ctypes.c_int32), ("copies", ctypes.c_int32), ("acc_split", ctypes.c_int32)]
 
 
 class ServerConfig(_Struct):

@@ -47,6 +47,7 @@ bool valid_plan(const kohler_plan &pl, int dtype, int32_t M) {
     if (pl.block != 256 && pl.block != 512 && pl.block != 1024) return false;
     if (pl.copies != 1 && pl.copies != 2 && pl.copies != 4) return false;
     if (pl.form != FORM_BAND && pl.copies != 1) return false;
+    if (pl.acc_split != 0 && pl.acc_split != 1) return false;
     if (pl.grid < 0 || pl.grid > 65535) return false;
     if (pl.replicas < 0 || pl.replicas > kMaxReplicas) return false;
     if (dtype == KOHLER_U8 && pl.px_per_lane != 4 && pl.px_per_lane != 8) return false;
@@ -280,7 +281,7 @@ int kohler_curve_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H,
     p.n = 1;
     p.M = M;
     p.cap = thr_capacity;
-    p.packed_acc = packable(H, W, nbhd) ? 1 : 0;
+    p.packed_acc = (!pl.acc_split && packable(H, W, nbhd)) ? 1 : 0;
     p.nrep = pl.replicas;
     p.rep_stride = replica_stride(M);
     p.acc_stride = (int64_t)p.nrep * p.rep_stride;
@@ -431,7 +432,7 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
     p.n = n;
     p.M = M;
     p.cap = thr_capacity;
-    p.packed_acc = 1;
+    p.packed_acc = pl.acc_split ? 0 : 1;
     for (int32_t i = 0; i < n; ++i)
         if (!packable(H[i], W[i], nbhd)) p.packed_acc = 0;
     p.nrep = nrep;

@@ -114,7 +114,7 @@ extern "C" int kohler_curve_noalloc(const void *d_img, int dtype, int64_t H, int
     p.band = pl.band;
     p.copies = pl.copies;
     p.cap = thr_capacity;
-    p.packed_acc = packable(H, W, nbhd) ? 1 : 0;
+    p.packed_acc = (!pl.acc_split && packable(H, W, nbhd)) ? 1 : 0;
     p.nrep = nrep;
     p.rep_stride = rstride;
     p.acc_stride = (int64_t)nrep * rstride;

@@ -133,7 +133,7 @@ struct Launch {
 
 // A graph is specific to an image shape, whether the image is already on the device, the lane and
 // the launch plan; buffers and the slot are updated in the instantiated graph before each replay.
-typedef std::tuple<int64_t, int64_t, int64_t, int, int, int, int, int, int, int, int, int> GraphKey;
+typedef std::tuple<int64_t, int64_t, int64_t, int, int, int, int, int, int, int, int, int, int> GraphKey;
 
 struct GraphEntry {
     hipGraph_t graph = nullptr;
@@ -222,6 +222,12 @@ const void *device_image(const kohler_server *s, const Item &it) {
     return it.on_device ? it.img : static_cast<const void *>(s->arena_base + it.arena_off);
 }
 
+// The graph of a one-image launch depends on the image's shape and residence, the lane and the plan.
+GraphKey graph_key(const Item &it, int lane, const kohler_plan &pl) {
+    return GraphKey(it.H, it.W, it.pitch, it.on_device ? 1 : 0, lane, pl.form, pl.band, pl.block, pl.grid,
+                    pl.px_per_lane, pl.replicas, pl.copies, pl.acc_split);
+}
+
 // Issue one launch (copies in, kernel, copies out, event) on `lane`. Runs without the lock.
 int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L) {
     const kohler_server_config &c = s->cfg;
@@ -236,15 +242,12 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
     }
     pl = resolve_plan(s->ctx, c.dtype, c.M, c.nbhd, units);
     KParams p = slot_params(s, pl);
-    p.packed_acc = packed ? 1 : 0;
+    p.packed_acc = (packed && !pl.acc_split) ? 1 : 0;
     p.total_units = units;
     hipError_t e = hipSuccess;
 
     if (n == 1 && c.use_graphs && (s->graphs.size() < kMaxGraphs ||
-                                   s->graphs.count(GraphKey(items[0].H, items[0].W, items[0].pitch,
-                                                            items[0].on_device, lane, pl.form, pl.band,
-                                                            pl.block, pl.grid, pl.px_per_lane, pl.replicas,
-                                                            pl.copies)))) {
+                                   s->graphs.count(graph_key(items[0], lane, pl)))) {
         const Item &it = items[0];
         p.n = 1;
         p.dyn = 1;
@@ -268,8 +271,7 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
         uint8_t *rec_h = s->rec_host + (size_t)it.slot * s->rec_bytes;
         void *img_dst = s->arena_base + it.arena_off;
 
-        const GraphKey key(it.H, it.W, it.pitch, it.on_device ? 1 : 0, lane, pl.form, pl.band, pl.block,
-                           pl.grid, pl.px_per_lane, pl.replicas, pl.copies);
+        const GraphKey key = graph_key(it, lane, pl);
         auto found = s->graphs.find(key);
         if (found == s->graphs.end()) {
             GraphEntry g;

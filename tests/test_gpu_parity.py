@@ -225,6 +225,87 @@ def test_cfg3_u16_m4096(ctx, nbhd):
 
 
 # ----------------------------------------------------------------------------------------------
+# two-word accumulators (D1 and E apart), the layout images with 2^30 or more pairs need, forced
+# with the plan's acc_split on images of every size
+
+@pytest.fixture
+def split_ctx(K):
+    c = K.Context(0)
+    yield c
+    c.close()
+
+
+def _split(ctx, K, dtype, M, nbhd, **kw):
+    ctx.set_plan(dtype, M, nbhd, acc_split=1, **kw)
+    assert ctx.get_plan(dtype, 64, 64, M, nbhd)["acc_split"] == 1
+
+
+def test_split_tiny_and_ragged(split_ctx, K):
+    rng = np.random.default_rng(77)
+    for M in (1, 2, 5, 37, 256):
+        for nbhd in (4, 8):
+            _split(split_ctx, K, 1, M, nbhd)
+    for H in range(1, 7):
+        for W in range(1, 7):
+            for M in (2, 5, 256):
+                for nbhd in (4, 8):
+                    img = rng.integers(0, M, size=(H, W)).astype(np.uint8)
+                    assert_result(split_ctx.curve(img, M, nbhd), reference(img, M, nbhd),
+                                  what=f"split {H}x{W} M={M} N{nbhd}")
+    for shape in SHAPES:
+        for M, nbhd in [(256, 4), (256, 8), (37, 4)]:
+            img = gen.random_image(rng, *shape, M, np.uint8, "smooth")
+            assert_result(split_ctx.curve(to_device(img), M, nbhd), reference(img, M, nbhd),
+                          what=f"split {shape} M={M} N{nbhd}")
+    for M, nbhd in [(4096, 4), (4096, 8), (700, 8)]:
+        _split(split_ctx, K, 2, M, nbhd)
+        img = gen.random_image(rng, 129, 513, M, np.uint16, "smooth")
+        assert_result(split_ctx.curve(to_device(img), M, nbhd), reference(img, M, nbhd),
+                      what=f"split u16 M={M} N{nbhd}")
+
+
+def test_split_plan_sweep(split_ctx, K):
+    rng = np.random.default_rng(78)
+    img = gen.random_image(rng, 301, 1283, 256, np.uint8, "smooth")
+    img[100:140, 200:900] = rng.integers(0, 256, size=(40, 700))
+    dev = to_device(img)
+    for nbhd in (4, 8):
+        ref = reference(img, 256, nbhd)
+        for form, band, copies in [(K.FORM_BAND, 32, 2), (K.FORM_BAND, 7, 4), (K.FORM_MARG, 0, 0),
+                                   (K.FORM_TRI, 0, 0)]:
+            for block, grid, ppl in [(256, 3, 4), (512, 0, 8), (1024, 0, 8)]:
+                if form == K.FORM_MARG and block == 1024:
+                    continue  # the marginal instances take at most 512 threads
+                if nbhd == 8 and ppl == 8 and block == 1024:
+                    continue  # so do the 8-neighbourhood ones with 8 pixels per lane
+                _split(split_ctx, K, 1, 256, nbhd, form=form, band=band, block=block, grid=grid,
+                       px_per_lane=ppl, copies=copies)
+                assert_result(split_ctx.curve(dev, 256, nbhd), ref,
+                              what=f"split plan {form},{band},{block},{grid},{ppl} N{nbhd}")
+
+
+def test_split_cfg2_and_batch(split_ctx, K):
+    img = gen.cfg2_image()
+    _split(split_ctx, K, 1, 256, 4)
+    res = split_ctx.curve(to_device(img), 256, 4)
+    d = _pins.pair_gaps(img, 4)
+    assert int(res.count.sum()) == int(d.sum()) and int(res.sum.sum()) == int((d * d // 4).sum())
+    assert_result(res, reference(img, 256, 4), what="split cfg2")
+    rng = np.random.default_rng(79)
+    imgs = [gen.random_image(rng, int(rng.integers(1, 200)), int(rng.integers(1, 900)), 256, np.uint8,
+                             "smooth") for _ in range(9)]
+    _batch_check(split_ctx, imgs, 256, 4)
+
+
+def test_split_cfg3_n8(split_ctx, K):
+    """The M > 256 finishing path with its second gather, on the 4096^2 12-bit workload."""
+    img = gen.cfg3_image()
+    _split(split_ctx, K, 2, 4096, 8)
+    res = split_ctx.curve(to_device(img), 4096, 8)
+    assert_result(res, reference(img, 4096, 8, exact_all=False), what="split cfg3 N8")
+
+
+# ----------------------------------------------------------------------------------------------
 # batched launch
 
 def _batch_check(ctx, imgs, M, nbhd, cap=None):
