@@ -52,8 +52,35 @@ def pct(x, q):
 # ------------------------------------------------------------------------------------------------
 # CPU baseline: the oracle as it stands
 
-def cpu_baseline(img: np.ndarray, M: int, nbhd: int, runs: int = 3) -> dict:
-    """The oracle (plain brute force of eqs (1)-(3), OpenMP over thresholds) on the host cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+ONE_THREAD_SNIPPET = """
+import sys, time, numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+img = np.load(sys.argv[2])
+oracle.curve(img[:8], int(sys.argv[3]), int(sys.argv[4]))
+t = time.perf_counter()
+oracle.curve(img, int(sys.argv[3]), int(sys.argv[4]))
+print(time.perf_counter() - t)
+"""
+
+
+def cpu_baseline(img: np.ndarray, M: int, nbhd: int, runs: int = 3, one_thread_rows: int = 864) -> dict:
+    """The oracle (plain brute force of eqs (1)-(3), OpenMP over thresholds) on the host cores, and
+    on one core (in a child process started with OMP_NUM_THREADS=1) over the first rows."""
+    import subprocess
+    import tempfile
+
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     times = []
@@ -62,10 +89,25 @@ def cpu_baseline(img: np.ndarray, M: int, nbhd: int, runs: int = 3) -> dict:
         oracle.curve(img, M, nbhd)
         times.append(time.perf_counter() - t)
     dt = float(np.median(times))
-    return {"value": img.size / dt / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
-            "seconds": dt,
-            "sample": f"the full {img.shape[0]}x{img.shape[1]} image, all {M} thresholds, "
-                      f"median of {runs} runs"}
+    res = {"value": img.size / dt / 1e9, "unit": "Gpixel/s", "cores": cores, "kind": "oracle",
+           "seconds": dt, "cpu_model": cpu_model(),
+           "sample": f"the full {img.shape[0]}x{img.shape[1]} image, all {M} thresholds, "
+                     f"median of {runs} runs"}
+    part = np.ascontiguousarray(img[:one_thread_rows])
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "rows.npy")
+        np.save(path, part)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        out = subprocess.run([sys.executable, "-c", ONE_THREAD_SNIPPET, ROOT, path, str(M), str(nbhd)],
+                             env=env, capture_output=True, text=True, timeout=600)
+    if out.returncode == 0:
+        t1 = float(out.stdout.strip().splitlines()[-1])
+        res["one_thread"] = {"value": part.size / t1 / 1e9, "unit": "Gpixel/s", "cores": 1, "seconds": t1,
+                             "sample": f"the first {part.shape[0]} rows ({part.shape[0]}x{part.shape[1]}), "
+                                       f"all {M} thresholds, one run"}
+    else:
+        res["one_thread"] = {"error": out.stderr.strip()[-300:]}
+    return res
 
 
 # ------------------------------------------------------------------------------------------------
@@ -101,6 +143,26 @@ def measured_traffic(plan: dict):
             return {"bytes": row["traffic_bytes_per_launch"],
                     "source": f"{t['method']}; measured with plan {row['plan']}"}
     return None
+
+
+def latency_ms(durs) -> dict:
+    d = np.asarray(durs) * 1e3
+    return {"n": int(len(d)), "mean": float(d.mean()), "p10": pct(d, 10), "p50": pct(d, 50), "p90": pct(d, 90),
+            "p99": pct(d, 99)}
+
+
+def lds_atomic_roofline(plan: dict, pairs: int, npx: int, kern_s: float, probe: dict) -> dict:
+    """LDS atomics per launch by the plan's form: one per pair for the joint histograms (banded,
+    triangular), two per pair plus one per pixel for the marginal histograms; the large-gap pass
+    of the banded form (two more per pair of gap > band) is not counted. Peak: the probe's
+    distinct-address rate (no two lanes of an instruction on one bank)."""
+    per_launch = (2 * pairs + npx) if plan.get("form") == 2 else pairs
+    achieved = per_launch / kern_s
+    return {"achieved": achieved, "peak": probe["distinct"], "unit": "atomics/s",
+            "frac": achieved / probe["distinct"], "atomics_per_launch": per_launch,
+            "probe": {k: probe[k] for k in ("distinct", "rand256", "band_table", "smooth_image", "same_word")},
+            "probe_launch": {"grid": probe["grid"], "block": probe["block"],
+                             "atomics_per_launch": probe["atomics_per_launch"]}}
 
 
 def parse_plan(s: str) -> dict:
@@ -150,23 +212,31 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
     torch.cuda.synchronize()
     t_begin = time.perf_counter()
     ev0.record(stream)
-    for i in range(args.steps):
-        ctx.curve_async(bufs[i % len(bufs)], M, nbhd, out=outs, stream=stream)
+    for i in range(args.steps):  # continue the rotation: the least recently used buffer first
+        ctx.curve_async(bufs[(args.warmup + i) % len(bufs)], M, nbhd, out=outs, stream=stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_begin
     kern = ev0.elapsed_time(ev1) * 1e-3 / args.steps  # seconds per launch
 
-    # frame latency: each launch bracketed by its own events (dispatch to completion)
-    nlat = min(args.steps, 100)
+    # frame latency: each launch bracketed by its own events (dispatch to completion), at least 100
+    nlat = max(100, min(args.steps, 1000))
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(nlat)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(nlat)]
     for i in range(nlat):
         starts[i].record(stream)
-        ctx.curve_async(bufs[i % len(bufs)], M, nbhd, out=outs, stream=stream)
+        ctx.curve_async(bufs[(args.warmup + args.steps + i) % len(bufs)], M, nbhd, out=outs, stream=stream)
         ends[i].record(stream)
     torch.cuda.synchronize()
     durs = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]) * 1e-3  # seconds
+
+    # the binding rooflines, measured in the same run: HBM read rate of a plain stream over the same
+    # rotated buffers, and the chip's LDS atomic rate (the pair phase adds one LDS counter per pair)
+    from paper_1707_05062_amd import roofline as roof
+    stream_rd = roof.read_stream(torch, bufs)
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    lds_probe = roof.lds_atomics(torch, ncu)
+    log(f"read stream {stream_rd['gb_s']:.0f} GB/s; LDS atomics distinct {lds_probe['distinct']:.3e}/s")
 
     if args.copy_probe:
         # a plain device copy of known size (one image buffer per dispatch), for scaling the
@@ -182,6 +252,8 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
     npx = H * W
     alg_bytes = npx * 1 + 3 * M * 8 + 4 * n_thr + 12  # pixels read once + curve and thresholds written
     achieved = alg_bytes / kern / 1e9
+    pairs = H * (W - 1) + (H - 1) * W
+    lds_atomic = lds_atomic_roofline(plan_used, pairs, npx, kern, lds_probe)
     traffic = measured_traffic(plan_used)
     if traffic:
         log(f"counter-measured traffic for this kernel build and plan: {traffic['bytes']:.0f} B/launch")
@@ -192,7 +264,7 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
         "ms_per_step": wall / args.steps * 1e3,
         "plan": plan_used,
         "tuning": tuned,
-        "frame_ms": {"p50": float(np.median(durs) * 1e3), "p99": float(np.percentile(durs, 99) * 1e3)},
+        "frame_ms": latency_ms(durs),
         "roofline": {
             "bound": "hbm",
             "achieved": achieved,
@@ -202,15 +274,103 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
             "traffic": traffic["bytes"] if traffic else None,
             "kernel_us": kern * 1e6,
             "alg_bytes_per_launch": alg_bytes,
+            "hbm_vs_stream_frac": achieved / stream_rd["gb_s"],
+            "read_stream": stream_rd,
+            "lds_atomic": lds_atomic,
         },
         "traffic_source": traffic["source"] if traffic else
             "null: no hardware-counter measurement for this kernel build and plan",
         "selfcheck": selfcheck,
         "segment": seg,
         "H": H, "W": W, "M": M, "nbhd": nbhd, "rotate_buffers": len(bufs),
+        "_lds_probe": lds_probe,
     }
     del bufs
     return res, img
+
+
+# ------------------------------------------------------------------------------------------------
+# the other single-image workloads: 256x256 u8, and 4096x4096 12-bit u16 (M = 4096) at N4 and N8
+
+def pair_gaps(img: np.ndarray, nbhd: int) -> np.ndarray:
+    f = img.astype(np.int64)
+    d = [np.abs(f[:, 1:] - f[:, :-1]).ravel(), np.abs(f[1:] - f[:-1]).ravel()]
+    if nbhd == 8:
+        d += [np.abs(f[1:, 1:] - f[:-1, :-1]).ravel(), np.abs(f[1:, :-1] - f[:-1, 1:]).ravel()]
+    return np.concatenate(d)
+
+
+def _dtype_code(a: np.ndarray) -> int:
+    from paper_1707_05062_amd import _lib
+    return _lib.U16 if a.dtype == np.uint16 else _lib.U8
+
+
+def config_line(K, torch, name: str, workload: str, img: np.ndarray, M: int, nbhd: int, lds_probe: dict,
+                reps: int = 200, rotate: int = 10) -> dict:
+    """One image per launch, autotuned plan, inputs resident and rotated over `rotate` copies;
+    kernel time from HIP events on the launch stream around `reps` back-to-back launches, plus 100
+    individually bracketed launches for the latency percentiles. Self-check: the closed-form totals
+    over the whole curve (sum_t count(t) = sum of the pair gaps, sum_t sum(t) = sum of floor(gap^2/4))."""
+    dev = torch.device("cuda", 0)
+    a = np.ascontiguousarray(img)
+    src = (torch.from_numpy(a.view(np.int16)).to(dev).view(torch.uint16) if a.dtype == np.uint16
+           else torch.from_numpy(a).to(dev))
+    bufs = [src.clone() for _ in range(rotate)]
+    H, W = a.shape
+    ctx = K.Context(0)
+    try:
+        plan, us = ctx.autotune([bufs[0]], M, nbhd, reps=3)
+        used = ctx.get_plan(_dtype_code(a), H, W, M, nbhd)
+        outs = ctx.alloc_outputs(M, M)
+        stream = torch.cuda.current_stream(dev)
+        ctx.curve_async(bufs[0], M, nbhd, out=outs, stream=stream)
+        torch.cuda.synchronize()
+        d = pair_gaps(a, nbhd)
+        n_thr, t0, status = [int(x) for x in outs["ints"].cpu()]
+        ok = bool(int(outs["count"].sum()) == int(d.sum()) and int(outs["sum"].sum()) == int((d * d // 4).sum())
+                  and status == 0)
+        for i in range(10):
+            ctx.curve_async(bufs[i % rotate], M, nbhd, out=outs, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(reps):
+            ctx.curve_async(bufs[(10 + i) % rotate], M, nbhd, out=outs, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kern = e0.elapsed_time(e1) * 1e-3 / reps
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(100)]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in range(100)]
+        for i in range(100):
+            starts[i].record(stream)
+            ctx.curve_async(bufs[i % rotate], M, nbhd, out=outs, stream=stream)
+            ends[i].record(stream)
+        torch.cuda.synchronize()
+        durs = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)]) * 1e-3
+    finally:
+        ctx.close()
+    npx = a.size
+    alg_bytes = npx * a.itemsize + 3 * M * 8 + 4 * n_thr + 12
+    log(f"{name}: {kern*1e6:.2f} us, {npx / kern / 1e9:.1f} Gpixel/s, selfcheck {ok}")
+    return {"workload": workload, "H": int(H), "W": int(W), "M": M, "nbhd": nbhd, "plan": used,
+            "tuning_median_us": us, "kernel_us": kern * 1e6, "gpixel_s": npx / kern / 1e9,
+            "frame_ms": latency_ms(durs),
+            "roofline": {"bound": "hbm", "achieved": alg_bytes / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg_bytes / kern / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes,
+                         "lds_atomic": lds_atomic_roofline(used, len(d), npx, kern, lds_probe)},
+            "thresholds": n_thr, "selfcheck": ok}
+
+
+def other_configs(K, torch, gen, lds_probe: dict) -> dict:
+    out = {"c1_256x256_u8_n4": config_line(
+        K, torch, "c1", "256x256 uint8, six constant rectangles + N(0,8^2) noise, M=256, 4-neighbourhood",
+        gen.cfg1_image(), 256, 4, lds_probe, reps=1000, rotate=4)}
+    c3 = gen.cfg3_image()
+    for nbhd in (4, 8):
+        out[f"c3_4096x4096_u16_m4096_n{nbhd}"] = config_line(
+            K, torch, f"c3 N{nbhd}", "4096x4096 uint16 12-bit, 500 Voronoi cells U[0,4095] + N(0,30^2) "
+            f"noise, M=4096, {nbhd}-neighbourhood", c3, 4096, nbhd, lds_probe)
+    return out
 
 
 # ------------------------------------------------------------------------------------------------
@@ -484,6 +644,7 @@ def run(args) -> dict:
 
     ctx = K.Context(0)
     head, img = headline(args, K, ctx, torch, gen)
+    lds_probe = head.pop("_lds_probe")
     result = {
         "metric": METRIC,
         "value": head["value"],
@@ -508,9 +669,20 @@ def run(args) -> dict:
         "roofline": head["roofline"],
         "selfcheck": head["selfcheck"],
         "segment": head["segment"],
-        "paper_context": {"fast_A_gpixel_s": 0.138, "hardware": "Intel i7-4702HQ 4C/8T",
-                          "image": "3672x4896 photograph (Table 1)"},
+        "paper_context": {
+            "hardware": "Intel Core i7-4702HQ, 2.20 GHz, 4 cores / 8 threads, 16 GB (Sec. 4)",
+            "image": "3672x4896 photograph, about 18 MP (Table 1)",
+            "fast_A_seconds": 0.130, "fast_A_gpixel_s": 0.138, "direct_D_seconds": 52.9,
+            "gain_A_vs_D_18mp": 405,
+            "video": {"frame": "502x480", "fast_A_frames_s": 96.96, "direct_D_frames_s": 0.99,
+                      "gain_A_vs_D": 96, "source": "Table 2 (the abstract's factor)"},
+            "this_run_vs_fast_A": None,
+            "note": "context only: the paper's own CPU timings, other hardware and another image",
+        },
     }
+    result["paper_context"]["this_run_vs_fast_A"] = head["value"] / 0.138
+    if args.only != "curve":
+        result["configs"] = other_configs(K, torch, gen, lds_probe)
     if args.only == "all":
         result["batched"] = batched(args, K, ctx, torch, gen)
         result["served"] = served(args, K, ctx, torch, gen)

@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(256) read_stream_kernel(const u32x4 *p, uint64
     if (x == never) sink[threadIdx.x & 63] = x;
 }
 
-// LDS address patterns (word indices into a table of kTableWords words):
+// LDS address patterns (word indices into a table of 33 rows of kRowWords words, dynamic LDS):
 enum Pattern : int {
     PAT_DISTINCT = 0,  // each lane of a wave its own consecutive word: no bank conflict, no collision
     PAT_RAND256 = 1,   // uniform over 256 words: collisions and bank conflicts of a 256-level histogram
@@ -40,7 +40,7 @@ enum Pattern : int {
                        // 16 of a level shared by the wave
     PAT_SAME = 4,      // every lane of a wave on one word
 };
-constexpr int kTableWords = 33 * 257;
+constexpr uint32_t kRowWords = 257;
 constexpr int kUnroll = 16;
 
 __device__ __forceinline__ uint32_t xorshift(uint32_t x) {
@@ -50,10 +50,14 @@ __device__ __forceinline__ uint32_t xorshift(uint32_t x) {
     return x;
 }
 
+// The table lives in dynamic LDS (after the one static word below) and its row length arrives as an
+// argument, so every pattern keeps one address register per unrolled increment.
 template <int PAT>
-__global__ void __launch_bounds__(1024) lds_atomic_kernel(int iters, uint32_t seed, uint32_t *out) {
-    __shared__ uint32_t tab[kTableWords];
-    for (int i = threadIdx.x; i < kTableWords; i += blockDim.x) tab[i] = 0;
+__global__ void __launch_bounds__(1024) lds_atomic_kernel(int iters, uint32_t seed, uint32_t *out,
+                                                          uint32_t row_words) {
+    extern __shared__ uint32_t tab[];
+    const uint32_t table_words = 33u * row_words;
+    for (uint32_t i = threadIdx.x; i < table_words; i += blockDim.x) tab[i] = 0;
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint32_t x = seed ^ (blockIdx.x * 0x9E3779B9u) ^ (threadIdx.x * 0x85EBCA6Bu) ^ 0x1234567u;
@@ -63,15 +67,15 @@ __global__ void __launch_bounds__(1024) lds_atomic_kernel(int iters, uint32_t se
         x = xorshift(x);
         uint32_t w;
         if constexpr (PAT == PAT_DISTINCT) {
-            w = (wave * 64u + lane + 1024u * (uint32_t)(k & 3)) % (uint32_t)kTableWords;
+            w = (wave * 64u + lane + 1024u * (uint32_t)(k & 3)) % table_words;
         } else if constexpr (PAT == PAT_RAND256) {
             w = x & 255u;
         } else if constexpr (PAT == PAT_BAND) {
-            w = (x >> 8) % (uint32_t)kTableWords;
+            w = (x >> 8) % table_words;
         } else if constexpr (PAT == PAT_SMOOTH) {
             const uint32_t centre = ((blockIdx.x * 7u + wave * 5u + (uint32_t)k * 13u) & 127u) + 32u;
             const uint32_t d = (x & 7u) + ((x >> 3) & 7u);
-            w = d * 257u + centre + ((x >> 6) & 15u);
+            w = d * row_words + centre + ((x >> 6) & 15u);
         } else {
             w = wave * 64u + (uint32_t)k;
         }
@@ -84,9 +88,16 @@ __global__ void __launch_bounds__(1024) lds_atomic_kernel(int iters, uint32_t se
     }
     __syncthreads();
     uint32_t s = 0;
-    for (int i = threadIdx.x; i < kTableWords; i += blockDim.x) s += tab[i];
-    // the table total is blockDim * iters * kUnroll; added up per workgroup so the atomics stay live
-    if (s) atomicAdd(out + blockIdx.x, s);
+    for (uint32_t i = threadIdx.x; i < table_words; i += blockDim.x) s += tab[i];
+    // the table total is blockDim * iters * kUnroll, added up per workgroup (so the atomics stay
+    // live) through one LDS word and ONE global atomic: a global atomic per thread on the same
+    // address would be serialised and take longer than the increments being measured
+    __shared__ uint32_t total;
+    if (threadIdx.x == 0) total = 0;
+    __syncthreads();
+    if (s) __hip_atomic_fetch_add(&total, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = total;
 }
 
 }  // namespace
@@ -102,16 +113,17 @@ int roof_read_stream(const void *d_buf, uint64_t bytes, int grid, int block, uin
 }
 
 // One launch of `grid` workgroups of `block` threads, each lane issuing iters * 16 LDS atomic
-// increments at `pattern`; d_out[grid] receives each workgroup's table total (zero it first).
+// increments at `pattern`; d_out[grid] receives each workgroup's table total.
 int roof_lds_atomics(int pattern, int iters, int grid, int block, uint32_t *d_out, void *stream) {
     if (iters < 1 || grid < 1 || block < 64 || block > 1024 || block % 64 != 0 || !d_out) return -1;
     const hipStream_t s = (hipStream_t)stream;
+    const size_t lds = 33u * kRowWords * sizeof(uint32_t);
     switch (pattern) {
-        case PAT_DISTINCT: hipLaunchKernelGGL(lds_atomic_kernel<PAT_DISTINCT>, dim3(grid), dim3(block), 0, s, iters, 7u, d_out); break;
-        case PAT_RAND256: hipLaunchKernelGGL(lds_atomic_kernel<PAT_RAND256>, dim3(grid), dim3(block), 0, s, iters, 7u, d_out); break;
-        case PAT_BAND: hipLaunchKernelGGL(lds_atomic_kernel<PAT_BAND>, dim3(grid), dim3(block), 0, s, iters, 7u, d_out); break;
-        case PAT_SMOOTH: hipLaunchKernelGGL(lds_atomic_kernel<PAT_SMOOTH>, dim3(grid), dim3(block), 0, s, iters, 7u, d_out); break;
-        case PAT_SAME: hipLaunchKernelGGL(lds_atomic_kernel<PAT_SAME>, dim3(grid), dim3(block), 0, s, iters, 7u, d_out); break;
+        case PAT_DISTINCT: hipLaunchKernelGGL(lds_atomic_kernel<PAT_DISTINCT>, dim3(grid), dim3(block), lds, s, iters, 7u, d_out, kRowWords); break;
+        case PAT_RAND256: hipLaunchKernelGGL(lds_atomic_kernel<PAT_RAND256>, dim3(grid), dim3(block), lds, s, iters, 7u, d_out, kRowWords); break;
+        case PAT_BAND: hipLaunchKernelGGL(lds_atomic_kernel<PAT_BAND>, dim3(grid), dim3(block), lds, s, iters, 7u, d_out, kRowWords); break;
+        case PAT_SMOOTH: hipLaunchKernelGGL(lds_atomic_kernel<PAT_SMOOTH>, dim3(grid), dim3(block), lds, s, iters, 7u, d_out, kRowWords); break;
+        case PAT_SAME: hipLaunchKernelGGL(lds_atomic_kernel<PAT_SAME>, dim3(grid), dim3(block), lds, s, iters, 7u, d_out, kRowWords); break;
         default: return -1;
     }
     return hipGetLastError() == hipSuccess ? 0 : -5;

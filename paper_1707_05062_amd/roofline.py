@@ -35,7 +35,9 @@ def load():
 
 
 def read_stream(torch, bufs, reps: int = 64, grid: int = 2048) -> dict:
-    """Median read rate (GB/s) of one launch reading one whole buffer, cycling over `bufs`."""
+    """Read rate (GB/s) of one launch reading one whole buffer, cycling over `bufs`: HIP events on
+    the launch stream around `reps` back-to-back launches (as the curve kernel is timed), so that
+    host launch latency stays out of the figure."""
     lib = load()
     dev = bufs[0].device
     sink = torch.zeros(64, dtype=torch.int32, device=dev)
@@ -44,48 +46,44 @@ def read_stream(torch, bufs, reps: int = 64, grid: int = 2048) -> dict:
     n16 = nbytes // 16 * 16
     for b in bufs[:4]:
         assert lib.roof_read_stream(b.data_ptr(), n16, grid, 256, sink.data_ptr(), stream.cuda_stream) == 0
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    a.record(stream)
     for i in range(reps):
-        ev[i][0].record(stream)
         assert lib.roof_read_stream(bufs[(4 + i) % len(bufs)].data_ptr(), n16, grid, 256, sink.data_ptr(),
                                     stream.cuda_stream) == 0
-        ev[i][1].record(stream)
+    b.record(stream)
     torch.cuda.synchronize()
-    import numpy as np
-    t = np.array([a.elapsed_time(b) * 1e-3 for a, b in ev])
-    med = float(np.median(t))
-    return {"bytes_per_launch": int(n16), "median_us": med * 1e6, "gb_s": n16 / med / 1e9,
-            "p10_gb_s": n16 / float(np.percentile(t, 90)) / 1e9,
-            "p90_gb_s": n16 / float(np.percentile(t, 10)) / 1e9, "grid": grid, "block": 256,
-            "launches": reps}
+    t = a.elapsed_time(b) * 1e-3 / reps
+    return {"bytes_per_launch": int(n16), "us_per_launch": t * 1e6, "gb_s": n16 / t / 1e9, "grid": grid,
+            "block": 256, "launches": reps, "buffers": len(bufs)}
 
 
-def lds_atomics(torch, num_cus: int, reps: int = 5, iters: int = 256, block: int = 1024,
+def lds_atomics(torch, num_cus: int, reps: int = 4, iters: int = 256, block: int = 1024,
                 per_cu: int = 2) -> dict:
-    """Chip-wide LDS atomic increments per second at each pattern (median of `reps` launches)."""
-    import numpy as np
+    """Chip-wide LDS atomic increments per second at each pattern: HIP events around `reps`
+    back-to-back launches (after one warm-up launch), each workgroup's count checked."""
     lib = load()
     dev = torch.device("cuda", torch.cuda.current_device())
     stream = torch.cuda.current_stream(dev)
     grid = num_cus * per_cu
-    out = torch.zeros(grid, dtype=torch.int32, device=dev)
+    outs = [torch.zeros(grid, dtype=torch.int32, device=dev) for _ in range(reps + 1)]
     per_iter = lib.roof_lds_atomics_per_iter()
     n = grid * block * iters * per_iter
-    res = {"grid": grid, "block": block, "atomics_per_launch": n}
+    res = {"grid": grid, "block": block, "atomics_per_launch": n, "launches": reps}
     for name, pat in PATTERNS.items():
-        ts = []
-        for r in range(reps + 1):
-            out.zero_()
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            assert lib.roof_lds_atomics(pat, iters, grid, block, out.data_ptr(), stream.cuda_stream) == 0
-            b.record(stream)
-            torch.cuda.synchronize()
-            if r:
-                ts.append(a.elapsed_time(b) * 1e-3)
-        total = int(out.to(torch.int64).sum())
-        assert total == n, f"LDS atomic probe {name}: counted {total}, expected {n}"
-        res[name] = n / float(np.median(ts))
+        for o in outs:
+            o.zero_()
+        assert lib.roof_lds_atomics(pat, iters, grid, block, outs[0].data_ptr(), stream.cuda_stream) == 0
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        for r in range(reps):
+            assert lib.roof_lds_atomics(pat, iters, grid, block, outs[r + 1].data_ptr(), stream.cuda_stream) == 0
+        b.record(stream)
+        torch.cuda.synchronize()
+        for o in outs:
+            total = int(o.to(torch.int64).sum())
+            assert total == n, f"LDS atomic probe {name}: counted {total}, expected {n}"
+        res[name] = n * reps / (a.elapsed_time(b) * 1e-3)
     return res
