@@ -5,7 +5,9 @@ product path (the HIP library and its Python binding) never does, and it shares 
 
 Reference: G. Noyel, arXiv 1707.05062. ``curve`` is the definition of Sec. 2.1 (eqs (1)-(3)) written
 out over every threshold and every ordered neighbour pair; ``alg1`` is Algorithm 1 of Sec. 3.1 over
-the half neighbourhood of Sec. 3.2; ``thresholds`` gives the curve's local maxima and the optimum of
+the half neighbourhood of Sec. 3.2; ``curve_nbhd`` and ``alg1_nbhd`` are the same two routes for
+a symmetric structuring element or the hexagonal 6-neighbourhood; ``binomial3`` is a 3x3 low-pass
+applied before the method (Sec. 5); ``thresholds`` gives the curve's local maxima and the optimum of
 eq (4); ``segment`` labels pixels by the classes those thresholds cut (Sec. 2.1), ``class_stats`` and
 ``mean_image`` give each class's mean value, ``top_thresholds`` the most significant thresholds. The
 C sources are in ``kohler_oracle.c``; ``build()`` compiles them with gcc and OpenMP.
@@ -55,6 +57,12 @@ def _bind(lib):
     lib.oracle_alg1.restype = ctypes.c_int
     lib.oracle_thresholds.argtypes = [i64p, i64p, ctypes.c_int32, i32p, ctypes.c_int32, i32p, i32p]
     lib.oracle_thresholds.restype = ctypes.c_int
+    lib.oracle_curve_nbhd.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, i32p, i32p,
+                                      ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32, i64p, i64p, f64p]
+    lib.oracle_curve_nbhd.restype = ctypes.c_int
+    lib.oracle_alg1_nbhd.argtypes = [i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, i32p, i32p,
+                                     ctypes.c_int32, ctypes.c_int32, i64p, i64p]
+    lib.oracle_alg1_nbhd.restype = ctypes.c_int
     return lib
 
 
@@ -103,6 +111,90 @@ def alg1(img: np.ndarray, M: int, nbhd: int = 4, lib=None):
     if st != OK:
         raise OracleError(st, "oracle_alg1")
     return s, k
+
+
+# ------------------------------------------------------------------------------------------------
+# Other neighbourhoods (Sec. 2.1 names the 6-neighbourhood; Sec. 3.2's argument holds for any
+# symmetric structuring element A and a half A* with one offset of each pair {a, -a}).
+
+def full_of(half) -> list[tuple[int, int]]:
+    """The symmetric set A = A* u -A* of a half set of (dy, dx) offsets."""
+    out = []
+    for dy, dx in half:
+        out += [(int(dy), int(dx)), (-int(dy), -int(dx))]
+    return out
+
+
+def half_of(full_) -> list[tuple[int, int]]:
+    """The canonical half of a symmetric set: the offsets with dy > 0, or dy == 0 and dx > 0."""
+    return [(int(dy), int(dx)) for dy, dx in full_ if dy > 0 or (dy == 0 and dx > 0)]
+
+
+def _offsets(offs):
+    o = np.asarray(offs, dtype=np.int32).reshape(-1, 2) if offs is not None and len(offs) else np.zeros((0, 2), np.int32)
+    return np.ascontiguousarray(o[:, 0]), np.ascontiguousarray(o[:, 1])
+
+
+def curve_nbhd(img: np.ndarray, M: int, offsets=None, hex: bool = False, ts=None, lib=None):
+    """Eqs (1)-(3) by enumeration over the full neighbourhood: the symmetric offset set `offsets`
+    ((dy, dx) pairs, the same at every pixel), or with hex=True the 6-neighbourhood of a hexagonal
+    grid stored with odd rows shifted right by half a pixel (see the C source). Returns (sum, count,
+    C) for t in ``ts`` (all of 0..M-1 by default)."""
+    lib = lib or _load()
+    f = np.ascontiguousarray(img, dtype=np.int32)
+    if f.ndim != 2:
+        raise ValueError("image must be 2-D")
+    dy, dx = _offsets(offsets)
+    t = np.arange(M, dtype=np.int32) if ts is None else np.ascontiguousarray(ts, dtype=np.int32)
+    s = np.zeros(len(t), np.int64)
+    k = np.zeros(len(t), np.int64)
+    c = np.zeros(len(t), np.float64)
+    st = lib.oracle_curve_nbhd(_ptr(f, ctypes.c_int32), f.shape[0], f.shape[1], M, _ptr(dy, ctypes.c_int32),
+                               _ptr(dx, ctypes.c_int32), len(dy), 1 if hex else 0, _ptr(t, ctypes.c_int32),
+                               len(t), _ptr(s, ctypes.c_int64), _ptr(k, ctypes.c_int64), _ptr(c, ctypes.c_double))
+    if st != OK:
+        raise OracleError(st, "oracle_curve_nbhd")
+    return s, k, c
+
+
+def alg1_nbhd(img: np.ndarray, M: int, half=None, hex: bool = False, lib=None):
+    """Algorithm 1 over a half neighbourhood (`half`: (dy, dx) offsets holding no offset with its
+    negation; hex=True: the hexagonal grid's half). Returns (sum, count)."""
+    lib = lib or _load()
+    f = np.ascontiguousarray(img, dtype=np.int32)
+    dy, dx = _offsets(half)
+    s = np.zeros(M, np.int64)
+    k = np.zeros(M, np.int64)
+    st = lib.oracle_alg1_nbhd(_ptr(f, ctypes.c_int32), f.shape[0], f.shape[1], M, _ptr(dy, ctypes.c_int32),
+                              _ptr(dx, ctypes.c_int32), len(dy), 1 if hex else 0, _ptr(s, ctypes.c_int64),
+                              _ptr(k, ctypes.c_int64))
+    if st != OK:
+        raise OracleError(st, "oracle_alg1_nbhd")
+    return s, k
+
+
+# ------------------------------------------------------------------------------------------------
+# A low-pass filter before the method (Sec. 5 suggests combining it with previous transforms; the
+# paper names no filter, so this one is a reading: the 3x3 binomial kernel).
+
+BINOMIAL3 = ((1, 2, 1), (2, 4, 2), (1, 2, 1))
+
+
+def binomial3(img: np.ndarray) -> np.ndarray:
+    """3x3 binomial low-pass: g(y, x) = floor((sum of w(i, j) f(y+i, x+j) over i, j in {-1, 0, 1}
+    + 8) / 16) with the weights BINOMIAL3 (total 16), i.e. the weighted mean rounded half up;
+    coordinates outside the image are replaced by the nearest pixel of the image (replicated
+    borders). Values stay in [0, M) when f does. Same shape and dtype as the input."""
+    a = np.asarray(img)
+    f = a.astype(np.int64)
+    H, W = f.shape
+    acc = np.zeros((H, W), np.int64)
+    for i in (-1, 0, 1):
+        ys = np.clip(np.arange(H) + i, 0, H - 1)
+        for j in (-1, 0, 1):
+            xs = np.clip(np.arange(W) + j, 0, W - 1)
+            acc += BINOMIAL3[i + 1][j + 1] * f[ys][:, xs]
+    return ((acc + 8) // 16).astype(a.dtype)
 
 
 def thresholds(sum_, count, cap: int | None = None, lib=None):

@@ -13,7 +13,13 @@ Sources of truth (G. Noyel, arXiv 1707.05062):
   - exact symmetries (transpose, flips, grey-level inversion, grey-level shift);
   - bounds (0 <= C(t) <= min(t, M-1-t), #B(M-1) = 0);
   - the half-neighbourhood theorem of Sec. 3.2 (eq (9)) via Algorithm 1 (Sec. 3.1);
-  - the direct route of Sec. 3.1: boundary pixels as the dilation of C_1^t minus C_1^t.
+  - the direct route of Sec. 3.1: boundary pixels as the dilation of C_1^t minus C_1^t;
+  - for other neighbourhoods (a symmetric structuring element, the hexagonal 6-neighbourhood):
+    hand-worked examples, eq (9) through Algorithm 1, the same closed forms over an independently
+    enumerated pair list, the direct route, and reductions to N4/N8 (the offset sets of N4 and N8,
+    and the hexagonal grid on one row or one column, which has only N4's pairs);
+  - for the 3x3 binomial pre-filter: hand-worked values, constant images, the impulse response,
+    the separable route, transposition and the value range.
 """
 from __future__ import annotations
 
@@ -261,8 +267,229 @@ def pin_direct_dilation(lib=None, seeds=range(10)):
             assert np.array_equal(s, sd) and np.array_equal(k, kd), ("dilation", seed, nbhd)
 
 
+# ----------------------------------------------------------------------------------------------
+# other neighbourhoods: a symmetric structuring element A with half A*, and the hexagonal grid
+
+N4_FULL = [(-1, 0), (1, 0), (0, -1), (0, 1)]
+N8_FULL = N4_FULL + [(-1, -1), (-1, 1), (1, -1), (1, 1)]
+
+
+def hex_neighbours(y: int) -> list[tuple[int, int]]:
+    """The hexagonal grid's neighbour offsets in row y, odd rows shifted right by half a pixel:
+    two in the row, and the two pixels of each adjacent row that touch this one (for an even row
+    the one below-left and the one below, as the odd row below sits half a pixel to the right)."""
+    if y % 2 == 0:
+        return [(0, -1), (0, 1), (-1, -1), (-1, 0), (1, -1), (1, 0)]
+    return [(0, -1), (0, 1), (-1, 0), (-1, 1), (1, 0), (1, 1)]
+
+
+def nbhd_pairs(img: np.ndarray, offs_of_row) -> list[tuple[int, int]]:
+    """Every unordered neighbour pair {p, q} once, as (f(p), f(q)), for a neighbourhood given by its
+    full offsets per row; the relation is symmetric, so each pair is seen from both ends and kept
+    from the end that comes first in raster order."""
+    H, W = img.shape
+    out = []
+    for y in range(H):
+        for x in range(W):
+            for dy, dx in offs_of_row(y):
+                y1, x1 = y + dy, x + dx
+                if 0 <= y1 < H and 0 <= x1 < W and (y1, x1) > (y, x):
+                    out.append((int(img[y, x]), int(img[y1, x1])))
+    return out
+
+
+def load_nbhd_fixture(name: str) -> dict:
+    d: dict = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = _parse_line(line)
+            d[k] = v
+    H, W = int(d["H"][0]), int(d["W"][0])
+    o = [int(x) for x in d.get("offsets", [])]
+    return dict(image=np.array([int(x) for x in d["image"]], dtype=np.int64).reshape(H, W),
+                M=int(d["M"][0]), hex=int(d["hex"][0]) == 1, offsets=list(zip(o[0::2], o[1::2])),
+                sum=np.array([int(x) for x in d["sum"]], np.int64),
+                count=np.array([int(x) for x in d["count"]], np.int64),
+                C=[Fraction(x) for x in d["C"]], thresholds=[int(x) for x in d.get("thresholds", [])],
+                t0=int(d["t0"][0]))
+
+
+def nbhd_fixture_names() -> list[str]:
+    return sorted(f for f in os.listdir(GOLDEN) if f.startswith("n") and f.endswith(".txt"))
+
+
+def pin_nbhd_golden(lib=None):
+    for fname in nbhd_fixture_names():
+        fx = load_nbhd_fixture(fname)
+        s, k, c = oracle.curve_nbhd(fx["image"], fx["M"], offsets=fx["offsets"], hex=fx["hex"], lib=lib)
+        assert np.array_equal(s, fx["sum"]) and np.array_equal(k, fx["count"]), (fname, s, k)
+        assert [float(q) for q in fx["C"]] == list(c), (fname, "C", c)
+        thr, t0, _, _ = oracle.thresholds(s, k, lib=lib)
+        assert list(thr) == fx["thresholds"] and t0 == fx["t0"], (fname, thr, t0)
+        half = None if fx["hex"] else oracle.half_of(fx["offsets"])
+        s1, k1 = oracle.alg1_nbhd(fx["image"], fx["M"], half=half, hex=fx["hex"], lib=lib)
+        assert np.array_equal(s1, fx["sum"]) and np.array_equal(k1, fx["count"]), (fname, "alg1")
+
+
+def random_half(rng, n_max: int = 6, r: int = 3) -> list[tuple[int, int]]:
+    """A random half set: distinct offsets with dy > 0, or dy == 0 and dx > 0, within radius r."""
+    cand = [(dy, dx) for dy in range(0, r + 1) for dx in range(-r, r + 1) if dy > 0 or dx > 0]
+    idx = rng.choice(len(cand), size=int(rng.integers(1, n_max + 1)), replace=False)
+    return [cand[i] for i in sorted(idx)]
+
+
+def pin_nbhd_alg1(lib=None, seeds=range(8)):
+    """Eq (9) for a symmetric A and for the hexagonal grid: the full ordered-pair definition equals
+    Algorithm 1 over the half."""
+    for seed in seeds:
+        rng = np.random.default_rng(6000 + seed)
+        M = int(rng.choice([2, 5, 16, 64, 256]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 14)), int(rng.integers(1, 14))))
+        half = random_half(rng)
+        s, k, _ = oracle.curve_nbhd(img, M, offsets=oracle.full_of(half), lib=lib)
+        s1, k1 = oracle.alg1_nbhd(img, M, half=half, lib=lib)
+        assert np.array_equal(s, s1) and np.array_equal(k, k1), ("alg1 offsets", seed, half)
+        s, k, _ = oracle.curve_nbhd(img, M, hex=True, lib=lib)
+        s1, k1 = oracle.alg1_nbhd(img, M, hex=True, lib=lib)
+        assert np.array_equal(s, s1) and np.array_equal(k, k1), ("alg1 hex", seed)
+
+
+def pin_nbhd_closed_forms(lib=None, seeds=range(6)):
+    """Over thresholds, sum_t #B(t) = sum of the gaps and sum_t sum(t) = sum of floor(d^2/4), with
+    the pairs listed independently (nbhd_pairs); and an isolated pixel of an otherwise constant
+    image has as many pairs as neighbours (6 inside the hexagonal grid)."""
+    for seed in seeds:
+        rng = np.random.default_rng(6100 + seed)
+        M = int(rng.choice([3, 16, 256]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 12)), int(rng.integers(1, 12))))
+        half = random_half(rng)
+        full = oracle.full_of(half)
+        for offs_of_row, kw in ((lambda y: full, dict(offsets=full)), (hex_neighbours, dict(hex=True))):
+            d = np.array([abs(a - b) for a, b in nbhd_pairs(img, offs_of_row)], np.int64)
+            s, k, _ = oracle.curve_nbhd(img, M, lib=lib, **kw)
+            assert int(k.sum()) == int(d.sum()), ("count total", seed, kw)
+            assert int(s.sum()) == int((d * d // 4).sum()), ("sum total", seed, kw)
+    for y, x in [(2, 3), (3, 3), (0, 3), (3, 0), (5, 6)]:
+        img = np.zeros((6, 7), np.int64)
+        img[y, x] = 9
+        _, k, _ = oracle.curve_nbhd(img, 10, hex=True, lib=lib)
+        deg = sum(1 for dy, dx in hex_neighbours(y) if 0 <= y + dy < 6 and 0 <= x + dx < 7)
+        assert list(k[:9]) == [deg] * 9 and not k[9:].any(), ("isolated pixel", y, x, deg)
+        if 0 < y < 5 and 0 < x < 6:
+            assert deg == 6
+
+
+def pin_nbhd_reductions(lib=None, seeds=range(4)):
+    """The offset sets of N4 and N8 give the 4- and 8-neighbourhood curves; the hexagonal grid on a
+    single row or a single column has only N4's pairs."""
+    for seed in seeds:
+        rng = np.random.default_rng(6200 + seed)
+        M = int(rng.choice([4, 32, 256]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 10)), int(rng.integers(1, 10))))
+        for full, nbhd in ((N4_FULL, 4), (N8_FULL, 8)):
+            s, k, c = oracle.curve_nbhd(img, M, offsets=full, lib=lib)
+            s0, k0, c0 = oracle.curve(img, M, nbhd, lib=lib)
+            assert np.array_equal(s, s0) and np.array_equal(k, k0) and np.array_equal(c, c0), (seed, nbhd)
+        for line in (img[:1], img[:, :1]):
+            s, k, _ = oracle.curve_nbhd(line, M, hex=True, lib=lib)
+            s0, k0, _ = oracle.curve(line, M, 4, lib=lib)
+            assert np.array_equal(s, s0) and np.array_equal(k, k0), ("hex line", seed, line.shape)
+
+
+def direct_by_dilation_rows(img: np.ndarray, M: int, offs_of_row):
+    """The direct route of Sec. 3.1 for a neighbourhood given per row: boundary pixels x0 are the
+    neighbours of C_1^t outside C_1^t, each paired with its neighbours in C_1^t."""
+    H, W = img.shape
+    sums, counts = [], []
+    for t in range(M):
+        c1 = {(y, x) for y in range(H) for x in range(W) if img[y, x] > t}
+        border = {(y + dy, x + dx) for (y, x) in c1 for (dy, dx) in offs_of_row(y)
+                  if 0 <= y + dy < H and 0 <= x + dx < W} - c1
+        S = K = 0
+        for (y, x) in border:
+            for (dy, dx) in offs_of_row(y):
+                q = (y + dy, x + dx)
+                if q in c1:
+                    S += min(int(img[q]) - t, t - int(img[y, x]))
+                    K += 1
+        sums.append(S)
+        counts.append(K)
+    return np.array(sums, np.int64), np.array(counts, np.int64)
+
+
+def pin_nbhd_direct(lib=None, seeds=range(6)):
+    for seed in seeds:
+        rng = np.random.default_rng(6300 + seed)
+        M = int(rng.choice([2, 3, 5, 8]))
+        img = rng.integers(0, M, size=(int(rng.integers(1, 6)), int(rng.integers(1, 6))))
+        full = oracle.full_of(random_half(rng, n_max=4, r=2))
+        for offs_of_row, kw in ((lambda y: full, dict(offsets=full)), (hex_neighbours, dict(hex=True))):
+            s, k, _ = oracle.curve_nbhd(img, M, lib=lib, **kw)
+            sd, kd = direct_by_dilation_rows(img, M, offs_of_row)
+            assert np.array_equal(s, sd) and np.array_equal(k, kd), ("direct", seed, kw)
+
+
 ALL_PINS = [pin_golden, pin_threshold_rule, pin_closed_form_totals, pin_special_cases,
-            pin_symmetries, pin_bounds, pin_alg1, pin_direct_dilation]
+            pin_symmetries, pin_bounds, pin_alg1, pin_direct_dilation, pin_nbhd_golden, pin_nbhd_alg1,
+            pin_nbhd_closed_forms, pin_nbhd_reductions, pin_nbhd_direct]
+
+
+# ----------------------------------------------------------------------------------------------
+# the 3x3 binomial pre-filter (Python oracle)
+
+def load_filter_cases() -> list[dict]:
+    cases, cur = [], {}
+    with open(os.path.join(GOLDEN, "f1_binomial3.txt")) as fh:
+        for line in fh:
+            line = line.strip()
+            if line.startswith("#"):
+                continue
+            if not line:
+                if cur:
+                    cases.append(cur)
+                cur = {}
+                continue
+            k, v = _parse_line(line)
+            cur[k] = v
+    if cur:
+        cases.append(cur)
+    out = []
+    for c in cases:
+        H, W = int(c["H"][0]), int(c["W"][0])
+        out.append(dict(name=c["case"][0], image=np.array([int(x) for x in c["image"]], np.uint8).reshape(H, W),
+                        out=np.array([int(x) for x in c["out"]], np.uint8).reshape(H, W)))
+    return out
+
+
+def pin_binomial3(filt=None, seeds=range(6)):
+    filt = filt or oracle.binomial3
+    for case in load_filter_cases():
+        assert np.array_equal(filt(case["image"]), case["out"]), case["name"]
+    # constant images are unchanged (weights add up to 16)
+    for v in (0, 1, 7, 255):
+        assert np.array_equal(filt(np.full((4, 5), v, np.uint8)), np.full((4, 5), v, np.uint8))
+    # impulse response: 16 at an interior pixel of zeros gives the kernel itself
+    imp = np.zeros((5, 5), np.uint16)
+    imp[2, 2] = 16
+    want = np.zeros((5, 5), np.uint16)
+    want[1:4, 1:4] = [[1, 2, 1], [2, 4, 2], [1, 2, 1]]
+    assert np.array_equal(filt(imp), want)
+    for seed in seeds:
+        rng = np.random.default_rng(6400 + seed)
+        H, W = int(rng.integers(1, 12)), int(rng.integers(1, 12))
+        img = rng.integers(0, 4096, size=(H, W)).astype(np.uint16)
+        g = filt(img)
+        # the separable route: [1 2 1] down the columns then along the rows, rounded once
+        f = np.pad(img.astype(np.int64), 1, mode="edge")
+        v = f[:-2] + 2 * f[1:-1] + f[2:]
+        hsum = v[:, :-2] + 2 * v[:, 1:-1] + v[:, 2:]
+        assert np.array_equal(g.astype(np.int64), (hsum + 8) // 16), ("separable", seed)
+        assert np.array_equal(filt(img.T), g.T), ("transpose", seed)
+        assert g.min() >= img.min() and g.max() <= img.max(), ("range", seed)
+        assert g.dtype == img.dtype and g.shape == img.shape
 
 
 # ------------------------------------------------------------------------------------------------

@@ -32,6 +32,15 @@ MUTANTS = {
                     "if (cmp_curve(sum[t], count[t], sum[best], count[best]) >= 0)"),
     "float_compare": ("const __int128 l = nu * dv, r = nv * du;",
                       "const __int128 l = (__int128)((double)nu / (double)du * 1e18), r = (__int128)((double)nv / (double)dv * 1e18);"),
+    # other neighbourhoods: the hexagonal grid's row parity, its half, and a generic offset's sign
+    "hex_parity_swapped": ("const int odd = (int)(y & 1);", "const int odd = (int)((y + 1) & 1);"),
+    "hex_half_wrong_diagonal": ("static const int HEY[3] = {0, 1, 1}, HEX_[3] = {1, -1, 0};",
+                                "static const int HEY[3] = {0, 1, 1}, HEX_[3] = {1, 1, 0};"),
+    "nbhd_offset_sign": ("const int64_t y1 = y + ody[a], x1 = x + odx[a];",
+                         "const int64_t y1 = y + ody[a], x1 = x - odx[a];"),
+    "nbhd_max_not_min": ("S += rise < fall ? rise : fall;", "S += rise < fall ? fall : rise;"),
+    "nbhd_alg1_range": ("for (int64_t t = lo; t < hi; ++t) { /* lo <= t < hi */",
+                        "for (int64_t t = lo + 1; t < hi; ++t) { /* lo <= t < hi */"),
 }
 
 
@@ -73,6 +82,10 @@ PY_MUTANTS = {
                         "return (-(int(sum_[t]) / c if c else 0.0), int(t))"),
     "top_tie_larger_t": ("top_thresholds", "return (-(Fraction(int(sum_[t]), c) if c else Fraction(0)), int(t))",
                          "return (-(Fraction(int(sum_[t]), c) if c else Fraction(0)), -int(t))"),
+    # the binomial pre-filter: round half up, replicated borders, the weights
+    "binomial_floor": ("binomial3", "return ((acc + 8) // 16).astype(a.dtype)", "return (acc // 16).astype(a.dtype)"),
+    "binomial_wrap": ("binomial3", "ys = np.clip(np.arange(H) + i, 0, H - 1)", "ys = (np.arange(H) + i) % H"),
+    "binomial_box": ("binomial3", "acc += BINOMIAL3[i + 1][j + 1] * f[ys][:, xs]", "acc += 16 * f[ys][:, xs] // 9"),
 }
 
 
@@ -88,7 +101,7 @@ def test_python_mutant_is_caught(name, monkeypatch):
     exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), ns)
     monkeypatch.setattr(oracle, fn, ns[fn])
     caught = []
-    for pin in (_pins.pin_segment, _pins.pin_class_stats):
+    for pin in (_pins.pin_segment, _pins.pin_class_stats, _pins.pin_binomial3):
         try:
             pin()
         except AssertionError as e:
@@ -108,3 +121,4 @@ def test_python_unmutated_copy_passes(fn, monkeypatch):
     monkeypatch.setattr(oracle, fn, ns[fn])
     _pins.pin_segment()
     _pins.pin_class_stats()
+    _pins.pin_binomial3()

@@ -37,6 +37,30 @@ def test_direct_dilation_route():
     _pins.pin_direct_dilation()
 
 
+def test_other_neighbourhoods_golden():
+    _pins.pin_nbhd_golden()
+
+
+def test_other_neighbourhoods_alg1():
+    _pins.pin_nbhd_alg1()
+
+
+def test_other_neighbourhoods_closed_forms():
+    _pins.pin_nbhd_closed_forms()
+
+
+def test_other_neighbourhoods_reductions():
+    _pins.pin_nbhd_reductions()
+
+
+def test_other_neighbourhoods_direct():
+    _pins.pin_nbhd_direct()
+
+
+def test_binomial_prefilter():
+    _pins.pin_binomial3()
+
+
 def test_same_double_fixture_is_meaningful():
     """The exact-compare fixture only tests something if the two values collide as doubles."""
     from fractions import Fraction
