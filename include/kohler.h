@@ -127,6 +127,42 @@ int kohler_curve_batch(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, co
                        kohler_stream_t stream);
 
 /*
+ * Other neighbourhoods and a pre-filter. Sec. 2.1 allows the 6-neighbourhood besides N4 and N8,
+ * and the argument of Sec. 3.2 (eqs (7)-(9): every unordered pair counted once through a half
+ * neighbourhood) holds for any symmetric structuring element A (a in A <=> -a in A) with a half A*
+ * holding one offset of each pair {a, -a}. Sec. 5 suggests combining the method with a previous
+ * low-pass filter; the one offered is a reading, the paper names none.
+ *   kind KOHLER_NBHD_OFFSETS  A = A* u -A*, A* given as n_half (dy, dx) offsets (1..16, each
+ *                             |dy|, |dx| <= 7, not (0, 0); an offset and its negation are the same
+ *                             pairs and may appear only once), the same at every pixel;
+ *   kind KOHLER_NBHD_HEX6     the 6-neighbourhood of a hexagonal grid stored on the H x W raster
+ *                             with the odd rows shifted right by half a pixel: a pixel of an even
+ *                             row y pairs with (y, x +- 1), (y +- 1, x - 1), (y +- 1, x); of an odd
+ *                             row with (y, x +- 1), (y +- 1, x), (y +- 1, x + 1).
+ *   prefilter 1: the curve of g = floor((sum of w f + 8) / 16) with the 3x3 binomial weights
+ *             w = [1 2 1; 2 4 2; 1 2 1] and replicated borders (coordinates outside the image
+ *             replaced by the nearest pixel) instead of f; g is computed on the fly, never stored.
+ * Pairs exist only between pixels of the image. Stream-ordered as kohler_curve_async, with the same
+ * device outputs and status values (a pixel >= M is a range error whether or not the filter is on);
+ * sizes as there, with M <= 8192. Returns KOHLER_OK, KOHLER_E_ARG (checked on the host, also a bad
+ * neighbourhood) or a launch error.
+ */
+enum kohler_nbhd_kind { KOHLER_NBHD_OFFSETS = 1, KOHLER_NBHD_HEX6 = 2 };
+#define KOHLER_NBHD_MAX_HALF 16
+
+typedef struct kohler_nbhd {
+    int32_t kind;
+    int32_t n_half;
+    int32_t half_dy[KOHLER_NBHD_MAX_HALF];
+    int32_t half_dx[KOHLER_NBHD_MAX_HALF];
+} kohler_nbhd;
+
+int kohler_curve_nbhd_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                            int32_t M, const kohler_nbhd *nbhd, int32_t prefilter, int64_t *d_sum,
+                            int64_t *d_count, double *d_C, int32_t *d_thr, int32_t thr_capacity,
+                            int32_t *d_n_thr, int32_t *d_t0, int32_t *d_status, kohler_stream_t stream);
+
+/*
  * Launch plan control (the autotuner's knobs). A plan fixes, for one (dtype, M, nbhd) family:
  *   form        0 = automatic, 1 = banded joint histogram (M <= 256), 2 = marginal histograms,
  *               3 = triangular joint histogram of (lo, hi) (M <= 256)

@@ -296,6 +296,52 @@ class Context:
             raise KohlerError(st, "kohler_curve_async")
         return out
 
+    def curve_nbhd_async(self, img, M: int, half=None, hex: bool = False, prefilter: bool = False,
+                         capacity: int | None = None, out=None, stream=None):
+        """Enqueue the curve of a device image for another neighbourhood: the symmetric structuring
+        element with half offsets `half` ((dy, dx) pairs), or hex=True for the hexagonal grid (odd
+        rows shifted right by half a pixel); prefilter=True takes the curve of the 3x3 binomial
+        low-pass of the image. Outputs as curve_async."""
+        torch = _torch()
+        ptr, code, H, W, pitch, keep = _image_args(img)
+        cap = M if capacity is None else int(capacity)
+        out = out or self.alloc_outputs(M, cap)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nb = _lib.Nbhd()
+        if hex:
+            nb.kind = _lib.NBHD_HEX6
+        else:
+            offs = [(int(dy), int(dx)) for dy, dx in (half or [])]
+            if len(offs) > _lib.NBHD_MAX_HALF:
+                raise ValueError(f"at most {_lib.NBHD_MAX_HALF} half offsets")
+            nb.kind = _lib.NBHD_OFFSETS
+            nb.n_half = len(offs)
+            for i, (dy, dx) in enumerate(offs):
+                nb.half_dy[i], nb.half_dx[i] = dy, dx
+        ints = out["ints"]
+        base = ints.data_ptr()
+        st = self._lib.kohler_curve_nbhd_async(
+            self._h, ctypes.c_void_p(ptr), code, H, W, pitch, M, ctypes.byref(nb), 1 if prefilter else 0,
+            _ptr(out["sum"]), _ptr(out["count"]), _ptr(out["C"]), _ptr(out["thr"]), cap, ctypes.c_void_p(base),
+            ctypes.c_void_p(base + 4), ctypes.c_void_p(base + 8), ctypes.c_void_p(s.cuda_stream))
+        del keep
+        if st != OK:
+            raise KohlerError(st, "kohler_curve_nbhd_async")
+        return out
+
+    def curve_nbhd(self, img, M: int, half=None, hex: bool = False, prefilter: bool = False,
+                   capacity: int | None = None, check: bool = True) -> CurveResult:
+        """curve_nbhd_async on torch's current stream, waited for; results as numpy arrays."""
+        torch = _torch()
+        out = self.curve_nbhd_async(img, M, half=half, hex=hex, prefilter=prefilter, capacity=capacity)
+        torch.cuda.current_stream(self.device).synchronize()
+        n, t0, st = [int(x) for x in out["ints"].cpu()]
+        if check and st not in (OK, E_CAPACITY):
+            raise KohlerError(st, "kohler_curve_nbhd_async")
+        cap = M if capacity is None else int(capacity)
+        return CurveResult(out["sum"].cpu().numpy(), out["count"].cpu().numpy(), out["C"].cpu().numpy(),
+                           out["thr"].cpu().numpy()[: min(n, cap)].copy(), t0, n, st)
+
     def curve_batch(self, imgs, M: int, nbhd: int = 4, capacity: int | None = None, out=None,
                     stream=None):
         """Enqueue the curves of n device images (one persistent launch). Outputs are [n, M] etc.;

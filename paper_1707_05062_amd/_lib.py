@@ -14,7 +14,7 @@ MAX_M_U16 = 10200
 # every symbol include/kohler.h declares
 EXPORTS = (
     "kohler_create", "kohler_destroy", "kohler_strerror", "kohler_curve", "kohler_curve_async",
-    "kohler_curve_batch", "kohler_curve_noalloc", "kohler_set_plan", "kohler_get_plan", "kohler_autotune", "kohler_segment",
+    "kohler_curve_batch", "kohler_curve_noalloc", "kohler_curve_nbhd_async", "kohler_set_plan", "kohler_get_plan", "kohler_autotune", "kohler_segment",
     "kohler_class_stats", "kohler_mean_image", "kohler_top_thresholds",
     "kohler_server_create", "kohler_server_destroy", "kohler_server_submit", "kohler_server_poll",
     "kohler_server_wait", "kohler_server_cancel", "kohler_server_pause", "kohler_server_stats",
@@ -24,6 +24,15 @@ EXPORTS = (
 class _Struct(ctypes.Structure):
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_ if k != "pad"}
+
+
+NBHD_OFFSETS, NBHD_HEX6 = 1, 2
+NBHD_MAX_HALF = 16
+
+
+class Nbhd(_Struct):
+    _fields_ = [("kind", ctypes.c_int32), ("n_half", ctypes.c_int32),
+                ("half_dy", ctypes.c_int32 * NBHD_MAX_HALF), ("half_dx", ctypes.c_int32 * NBHD_MAX_HALF)]
 
 
 class Plan(_Struct):
@@ -88,6 +97,9 @@ def load(path: str = LIB_PATH):
     lib.kohler_curve_noalloc.argtypes = [vp, ctypes.c_int, i64, i64, i64, i32, i32, vp, vp, vp, vp, i32, vp, vp,
                                          vp, ctypes.POINTER(Plan), vp]
     lib.kohler_curve_noalloc.restype = ctypes.c_int
+    lib.kohler_curve_nbhd_async.argtypes = [vp, vp, ctypes.c_int, i64, i64, i64, i32, ctypes.POINTER(Nbhd), i32,
+                                            vp, vp, vp, vp, i32, vp, vp, vp, vp]
+    lib.kohler_curve_nbhd_async.restype = ctypes.c_int
     lib.kohler_set_plan.argtypes = [vp, ctypes.c_int, i32, i32, ctypes.POINTER(Plan)]
     lib.kohler_set_plan.restype = ctypes.c_int
     lib.kohler_get_plan.argtypes = [vp, ctypes.c_int, i64, i64, i32, i32, ctypes.POINTER(Plan)]

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -301,6 +302,123 @@ int kohler_curve_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H,
     p.t0 = d_t0;
     p.status = d_status;
     return launch(ctx, p, dtype, nbhd, pl, stream);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Other neighbourhoods and the pre-filter
+
+namespace {
+
+// The kernel's offset tables for a neighbourhood description; false if the description is invalid.
+bool nbhd_params(const kohler_nbhd &nb, NbParams &q) {
+    int hy[2][kNbMaxHalf], hx[2][kNbMaxHalf], nh[2];
+    if (nb.kind == KOHLER_NBHD_HEX6) {
+        // odd rows shifted right by half a pixel: (0, 1), then the two touching pixels of the row below
+        static const int EY[3] = {0, 1, 1}, EX[3] = {1, -1, 0}, OY[3] = {0, 1, 1}, OX[3] = {1, 0, 1};
+        for (int a = 0; a < 3; ++a) {
+            hy[0][a] = EY[a], hx[0][a] = EX[a];
+            hy[1][a] = OY[a], hx[1][a] = OX[a];
+        }
+        nh[0] = nh[1] = 3;
+    } else if (nb.kind == KOHLER_NBHD_OFFSETS) {
+        if (nb.n_half < 1 || nb.n_half > KOHLER_NBHD_MAX_HALF) return false;
+        for (int a = 0; a < nb.n_half; ++a) {
+            int dy = nb.half_dy[a], dx = nb.half_dx[a];
+            if (dy == 0 && dx == 0) return false;
+            if (dy < -kNbMaxRadius || dy > kNbMaxRadius || dx < -kNbMaxRadius || dx > kNbMaxRadius) return false;
+            if (dy < 0 || (dy == 0 && dx < 0)) dy = -dy, dx = -dx;  // the same unordered pairs
+            for (int b = 0; b < a; ++b)
+                if (hy[0][b] == dy && hx[0][b] == dx) return false;  // an offset given twice (or with its negation)
+            hy[0][a] = hy[1][a] = dy;
+            hx[0][a] = hx[1][a] = dx;
+        }
+        nh[0] = nh[1] = nb.n_half;
+    } else {
+        return false;
+    }
+    // the whole neighbourhood of a pixel in a row of parity par: its half offsets, and the negated
+    // half offsets of the row each one comes from (y - dy)
+    q.radius = 0;
+    for (int par = 0; par < 2; ++par) {
+        q.nhalf[par] = nh[par];
+        int nf = 0;
+        for (int a = 0; a < nh[par]; ++a) {
+            q.hdy[par][a] = (int8_t)hy[par][a];
+            q.hdx[par][a] = (int8_t)hx[par][a];
+            q.fdy[par][nf] = (int8_t)hy[par][a];
+            q.fdx[par][nf++] = (int8_t)hx[par][a];
+            q.radius = std::max(q.radius, std::max(hy[par][a], std::abs(hx[par][a])));
+        }
+        for (int src = 0; src < 2; ++src)
+            for (int a = 0; a < nh[src]; ++a)
+                if (((hy[src][a] & 1) ? 1 - par : par) == src) {  // row y - dy has parity src
+                    q.fdy[par][nf] = (int8_t)-hy[src][a];
+                    q.fdx[par][nf++] = (int8_t)-hx[src][a];
+                }
+        q.nfull[par] = nf;
+    }
+    return true;
+}
+
+}  // namespace
+
+int kohler_curve_nbhd_async(kohler_ctx *ctx, const void *d_img, int dtype, int64_t H, int64_t W, int64_t pitch,
+                            int32_t M, const kohler_nbhd *nbhd, int32_t prefilter, int64_t *d_sum,
+                            int64_t *d_count, double *d_C, int32_t *d_thr, int32_t thr_capacity,
+                            int32_t *d_n_thr, int32_t *d_t0, int32_t *d_status, kohler_stream_t stream) {
+    if (!ctx || !d_img || !nbhd || !valid_shape(dtype, H, W, pitch, M, 4)) return KOHLER_E_ARG;
+    if (M > kNbMaxM || (prefilter != 0 && prefilter != 1)) return KOHLER_E_ARG;
+    if (!d_sum || !d_count || !d_C || !d_n_thr || !d_t0 || !d_status) return KOHLER_E_ARG;
+    if (thr_capacity < 0 || (thr_capacity > 0 && !d_thr)) return KOHLER_E_ARG;
+    NbParams q{};
+    if (!nbhd_params(*nbhd, q)) return KOHLER_E_ARG;
+    const int form = M <= kMaxMBand ? FORM_TRI : FORM_MARG;
+    const int block = kNbBlock;
+    q.filter = prefilter;
+    q.k.M = M;
+    const size_t lds = nbhd_lds_layout(q, form, block);
+    if (lds > kMaxLdsBytes) return KOHLER_E_ARG;
+    q.tiles_x = (W + block - 1) / block;
+    q.tiles = ((H + q.tile_rows - 1) / q.tile_rows) * q.tiles_x;
+    const int nmax = std::max(q.nhalf[0], q.nhalf[1]);
+    // LDS counters are 32-bit: a workgroup sees at most 4 * nmax increments per pixel (a pair's
+    // counters, or a pixel's degree in the marginal form)
+    const int64_t px_per_wg_max = (int64_t(1) << 31) / (4 * nmax);
+    const int64_t min_grid = (H * W + px_per_wg_max - 1) / px_per_wg_max + 1;
+    const int per_cu = nbhd_blocks_per_cu(dtype, form, M, block, lds);
+    int64_t grid = std::min<int64_t>(q.tiles, (int64_t)ctx->num_cus * per_cu);
+    grid = std::max<int64_t>(grid, std::min<int64_t>(min_grid, q.tiles));
+    if (grid > 65535) return KOHLER_E_ARG;
+
+    KParams &p = q.k;
+    p.imgs = nullptr;
+    p.img0 = describe(d_img, dtype, H, W, pitch, 4, 0);
+    p.n = 1;
+    p.cap = thr_capacity;
+    p.packed_acc = (int64_t)nmax * H * W < (int64_t(1) << 30) ? 1 : 0;
+    p.nrep = replicas_for((int)grid);
+    p.rep_stride = replica_stride(M);
+    p.acc_stride = (int64_t)p.nrep * p.rep_stride;
+    p.total_units = q.tiles;
+    p.acc = ctx->acc1;
+    p.done = ctx->done1;
+    p.rflag = ctx->rflag1;
+    p.dyn = 1;
+    p.band = 1;
+    p.copies = 1;
+    p.ostride = M;
+    p.istride = 1;
+    p.thr_stride = thr_capacity;
+    p.sum = d_sum;
+    p.count = d_count;
+    p.C = d_C;
+    p.thr = d_thr;
+    p.n_thr = d_n_thr;
+    p.t0 = d_t0;
+    p.status = d_status;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return pick_status(e);
+    return pick_status(launch_nbhd(q, dtype, form, block, (int)grid, lds, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int kohler_curve(kohler_ctx *ctx, const void *img, int dtype, int64_t H, int64_t W, int64_t pitch,

@@ -126,6 +126,41 @@ int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int ban
 hipError_t curve_kernel_for(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block,
                             int copies, const void **func, size_t *lds);
 
+// ------------------------------------------------------------------------------------------------
+// Other neighbourhoods and the pre-filter (one image per launch, nbhd_kernel): the pairs of a
+// symmetric structuring element given by its half, or of the hexagonal grid (half offsets that
+// depend on the row's parity), over tiles of tile_rows x blockDim pixels staged in LDS as 16-bit
+// values (raw, or through the 3x3 binomial pre-filter). Joint (triangular) table for M <= 256,
+// marginal histograms above.
+
+constexpr int kNbMaxHalf = 16;    // half offsets per row parity
+constexpr int kNbMaxRadius = 7;   // largest |dx| and dy of a half offset
+constexpr int kNbBlock = 512;     // threads per workgroup = tile columns
+constexpr int kNbMaxM = 8192;     // marginal tables plus the tile fit the LDS
+
+struct NbParams {
+    KParams k;                    // the image, scratch and outputs as for a single-image curve launch
+    int32_t nhalf[2];             // half offsets of even and odd rows
+    int32_t nfull[2];             // whole-neighbourhood offsets of even and odd rows (pixel degrees)
+    int8_t hdy[2][kNbMaxHalf], hdx[2][kNbMaxHalf];
+    int8_t fdy[2][2 * kNbMaxHalf], fdx[2][2 * kNbMaxHalf];
+    int32_t radius;               // largest |dx| and dy over the half offsets
+    int32_t filter;               // 1: 3x3 binomial pre-filter, rounded half up, replicated borders
+    int32_t tile_rows;            // image rows per tile
+    uint32_t tile_off;            // LDS byte offset of the value tile
+    uint32_t bs_off;              // LDS byte offset of the workgroup scratch
+    int32_t pad;
+    int64_t tiles_x, tiles;       // tiles per band of tile_rows rows, and in all
+};
+
+// LDS layout of an nbhd_kernel launch: fills tile_rows, tile_off and bs_off and returns the bytes.
+size_t nbhd_lds_layout(NbParams &q, int form, int block);
+// Workgroups of an nbhd_kernel instance that fit on one compute unit.
+int nbhd_blocks_per_cu(int dtype, int form, int M, int block, size_t lds);
+// Launch nbhd_kernel (every field of q set). Returns hipSuccess or the launch error.
+hipError_t launch_nbhd(const NbParams &q, int dtype, int form, int block, int grid, size_t lds,
+                       hipStream_t stream);
+
 // Launch the curve kernel (p.band and p.copies already set). Returns hipSuccess or the launch error.
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,
                         int grid, hipStream_t stream);

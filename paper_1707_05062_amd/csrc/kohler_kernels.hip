@@ -1473,6 +1473,60 @@ __device__ __forceinline__ KImage image_desc(const KParams &p, int i) {
     return im;
 }
 
+// Zeroes the first `words` (a multiple of 4) words of the workgroup's LDS and the chunk counter.
+__device__ __forceinline__ void clear_lds(lds_u32 *lds, LdsScratch &bs, uint32_t words) {
+    for (uint32_t x = threadIdx.x; x < words / 4; x += blockDim.x)
+        reinterpret_cast<KOHLER_LDS u32x4 *>(lds)[x] = u32x4{0u, 0u, 0u, 0u};
+    if (threadIdx.x == 0) bs.next = 0;
+    lds_barrier();
+    phase_stamp(1);
+}
+
+// After the pair work of `units` units of image im (of `expected` in the whole launch, counted in
+// the ticket): range flag, merge into the image's accumulators, ticket, and the finalize step when
+// this workgroup completed the image. Called by every thread of the workgroup.
+template <int FORM, bool CLAMP>
+__device__ __forceinline__ void flush_image(const KParams &p, lds_u32 *lds, LdsScratch &bs, const KImage &im,
+                                            uint32_t vmax, int64_t units, int64_t expected) {
+    const uint32_t Mm1 = (uint32_t)p.M - 1u;
+    const int i = im.out;
+    uint64_t sink = 0;
+    if constexpr (CLAMP) {
+        vmax = wave_max(vmax);
+        if ((threadIdx.x & 63) == 0 && vmax > Mm1)
+            sink = __hip_atomic_fetch_or(gptr(p.rflag + i), 1u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
+    }
+    __syncthreads();
+    phase_stamp(2);
+    if (units == 0) return;  // uniform: nothing to add, and no ticket to take
+    int64_t *acc_g = p.acc + (int64_t)i * p.acc_stride + (int64_t)(blockIdx.x % (uint32_t)p.nrep) * p.rep_stride;
+    if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
+    else if constexpr (FORM == FORM_TRI) sink ^= merge_tri(p, lds, acc_g);
+    else sink ^= merge_marg(p, lds, acc_g);
+
+    // every contribution of this workgroup has been performed once its returned value is here:
+    // consuming the values makes the wave wait for all of them before the barrier
+    asm volatile("" ::"v"((uint32_t)sink), "v"((uint32_t)(sink >> 32)));
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    phase_stamp(4);
+    if (threadIdx.x == 0) {
+        const unsigned long long old = add_shared(p.done + i, (unsigned long long)units);
+        bs.last = (old + (unsigned long long)units == (unsigned long long)expected) ? 1 : 0;
+    }
+    __syncthreads();
+    phase_stamp(5);
+    if (bs.last) {
+        if constexpr (FORM == FORM_MARG) {
+            if (p.M <= kFinMaxM) finalize_small(p, i, lds);
+            else finalize(p, i, lds, bs);
+        } else {
+            finalize_small(p, i, lds);
+        }
+    }
+    __syncthreads();
+}
+
 // Largest workgroup of an instance: 1024 threads where the registers fit four waves per SIMD without
 // spilling, else 512 (the marginal form and the 8-neighbourhood with 8 pixels per lane).
 template <int NB, int K, int FORM>
@@ -1504,13 +1558,7 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
     else if constexpr (FORM == FORM_TRI) table_words = (tri_words((uint32_t)p.M) + 64u + 3u) & ~3u;
     else table_words = 4u * (uint32_t)p.M;
 
-    auto clear_tables = [&]() {
-        for (uint32_t x = threadIdx.x; x < table_words / 4; x += blockDim.x)
-            reinterpret_cast<KOHLER_LDS u32x4 *>(lds)[x] = u32x4{0u, 0u, 0u, 0u};
-        if (threadIdx.x == 0) bs.next = 0;
-        lds_barrier();
-        phase_stamp(1);
-    };
+    auto clear_tables = [&]() { clear_lds(lds, bs, table_words); };
 
     // Runs `chunks(acc, spill, vmax)` with the accumulators of this kernel's form; it must feed every
     // pair of the units the wave takes on.
@@ -1540,46 +1588,8 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
         return vmax;
     };
 
-    // After the pair work of `units` units of image im (of `expected` in the whole launch, counted in
-    // the ticket): range flag, merge into the image's accumulators, ticket, and the finalize step
-    // when this workgroup completed the image.
     auto flush = [&](const KImage &im, uint32_t vmax, int64_t units, int64_t expected) {
-        const int i = im.out;
-        uint64_t sink = 0;
-        if constexpr (CLAMP) {
-            vmax = wave_max(vmax);
-            if ((threadIdx.x & 63) == 0 && vmax > Mm1)
-                sink = __hip_atomic_fetch_or(gptr(p.rflag + i), 1u, __ATOMIC_RELAXED, KOHLER_XSCOPE);
-        }
-        __syncthreads();
-        phase_stamp(2);
-        if (units == 0) return;  // uniform: nothing to add, and no ticket to take
-        int64_t *acc_g = p.acc + (int64_t)i * p.acc_stride + (int64_t)(blockIdx.x % (uint32_t)p.nrep) * p.rep_stride;
-        if constexpr (FORM == FORM_BAND) sink ^= merge_band(p, lds, acc_g);
-        else if constexpr (FORM == FORM_TRI) sink ^= merge_tri(p, lds, acc_g);
-        else sink ^= merge_marg(p, lds, acc_g);
-
-        // every contribution of this workgroup has been performed once its returned value is here:
-        // consuming the values makes the wave wait for all of them before the barrier
-        asm volatile("" ::"v"((uint32_t)sink), "v"((uint32_t)(sink >> 32)));
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        phase_stamp(4);
-        if (threadIdx.x == 0) {
-            const unsigned long long old = add_shared(p.done + i, (unsigned long long)units);
-            bs.last = (old + (unsigned long long)units == (unsigned long long)expected) ? 1 : 0;
-        }
-        __syncthreads();
-        phase_stamp(5);
-        if (bs.last) {
-            if constexpr (FORM == FORM_MARG) {
-                if (p.M <= kFinMaxM) finalize_small(p, i, lds);
-                else finalize(p, i, lds, bs);
-            } else {
-                finalize_small(p, i, lds);
-            }
-        }
-        __syncthreads();
+        flush_image<FORM, CLAMP>(p, lds, bs, im, vmax, units, expected);
     };
 
     // rows a wave processes at a time: a chunk of the single-image launch, a claim of the batched one
@@ -1674,6 +1684,129 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
     }
 }
 
+// ------------------------------------------------------------------------------------------------
+// Other neighbourhoods and the pre-filtered image (NbParams): one image per launch. The image is cut
+// into tiles of tile_rows x blockDim pixels, dealt round-robin to the workgroups. A tile's values
+// (rows r0 .. r0 + tile_rows + radius - 1, columns c0 - radius .. c0 + blockDim + radius - 1, the
+// ones a pair of its pixels can reach) are staged in LDS as 16-bit values, each read once from
+// memory, or computed through the 3x3 binomial pre-filter; then every thread walks its column of
+// the tile and adds, for each pixel, the pairs of its row's half offsets (Sec. 3.2 eqs (7)-(9):
+// each unordered pair once) into the joint (triangular) or the marginal tables of the workgroup.
+
+// One pixel of the image (element index y * pitch + x).
+template <typename Pix>
+__device__ __forceinline__ uint32_t image_px(const KImage &im, int64_t y, int64_t x) {
+    return (uint32_t)gptr(static_cast<const Pix *>(im.ptr) + y * im.pitch)[(uint32_t)x];
+}
+
+// The 3x3 binomial low-pass at (y, x): weights 1 2 1 / 2 4 2 / 1 2 1, coordinates outside the image
+// replaced by the nearest pixel of the image, (sum + 8) >> 4. `centre` receives f(y, x).
+template <typename Pix>
+__device__ __forceinline__ uint32_t binomial3_at(const KImage &im, int64_t y, int64_t x, uint32_t &centre) {
+    const int64_t ys[3] = {y > 0 ? y - 1 : 0, y, y + 1 < im.H ? y + 1 : im.H - 1};
+    const int64_t xs[3] = {x > 0 ? x - 1 : 0, x, x + 1 < im.W ? x + 1 : im.W - 1};
+    uint32_t rows[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const uint32_t a = image_px<Pix>(im, ys[i], xs[0]), b = image_px<Pix>(im, ys[i], xs[1]),
+                       c = image_px<Pix>(im, ys[i], xs[2]);
+        if (i == 1) centre = b;
+        rows[i] = a + 2u * b + c;
+    }
+    return (rows[0] + 2u * rows[1] + rows[2] + 8u) >> 4;
+}
+
+template <typename Pix, int FORM, bool CLAMP>
+__global__ void __launch_bounds__(kNbBlock) nbhd_kernel(NbParams q) {
+    extern __shared__ __align__(16) uint32_t lds_raw[];
+    lds_u32 *lds = (lds_u32 *)lds_raw;
+    const KParams &p = q.k;
+    LdsScratch &bs = *reinterpret_cast<LdsScratch *>(reinterpret_cast<KOHLER_LDS uint8_t *>(lds) + q.bs_off);
+    if ((uint32_t)(size_t)lds != 0u) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) p.status[(int64_t)p.img0.out * p.istride] = ST_LAYOUT;
+        return;
+    }
+    const int G = gridDim.x;
+    const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+    const uint32_t Mm1 = (uint32_t)p.M - 1u;
+    const uint32_t table_words = FORM == FORM_TRI ? (tri_words((uint32_t)p.M) + 64u + 3u) & ~3u : 4u * (uint32_t)p.M;
+    clear_lds(lds, bs, table_words);
+
+    const KImage im = image_desc(p, 0);
+    const int64_t H = im.H, W = im.W;
+    const int R = q.radius, TH = q.tile_rows, TW = (int)blockDim.x, TC = TW + 2 * R;
+    KOHLER_LDS uint16_t *tile = reinterpret_cast<KOHLER_LDS uint16_t *>(reinterpret_cast<KOHLER_LDS uint8_t *>(lds) +
+                                                                        q.tile_off);
+    typedef typename std::conditional<FORM == FORM_TRI, TriAcc, MargAcc>::type Acc;
+    Acc acc = [&]() {
+        if constexpr (FORM == FORM_TRI) return TriAcc{2u * tri_words((uint32_t)p.M), 0u, 0u};
+        else return MargAcc{lds, lds + p.M, lds + 2 * p.M, 0u, 0u};
+    }();
+    uint32_t vmax = 0;
+    int64_t mine = 0;
+    for (int64_t t = g; t < q.tiles; t += G, ++mine) {
+        const int64_t ty = t / q.tiles_x, tx = t - ty * q.tiles_x;
+        const int64_t r0 = ty * TH, c0 = tx * TW;
+        // 1. the tile's values; each image pixel is range-checked by the tile that owns it
+        for (int i = (int)threadIdx.x; i < (TH + R) * TC; i += TW) {
+            const int ry = i / TC, rx = i - ry * TC;
+            const int64_t y = r0 + ry, x = c0 - R + rx;
+            uint32_t v = 0;
+            if (y < H && x >= 0 && x < W) {
+                uint32_t raw;
+                if (q.filter) v = binomial3_at<Pix>(im, y, x, raw);
+                else v = raw = image_px<Pix>(im, y, x);
+                if constexpr (CLAMP) {
+                    if (ry < TH && rx >= R && rx < R + TW) vmax = max(vmax, raw);
+                    v = min(v, Mm1);
+                }
+            }
+            tile[i] = (uint16_t)v;
+        }
+        __syncthreads();
+        // 2. the pairs of the tile's own pixels, one column per thread
+        const int64_t x = c0 + threadIdx.x;
+        const bool inx = x < W;
+        for (int ry = 0; ry < TH; ++ry) {
+            const int64_t y = r0 + ry;
+            if (y >= H) break;  // uniform
+            const int par = (int)(y & 1);
+            const uint32_t v = tile[ry * TC + R + (int)threadIdx.x];
+            const typename Acc::P pv = Acc::prep(v);
+            for (int a = 0; a < q.nhalf[par]; ++a) {
+                const int dy = q.hdy[par][a], dx = q.hdx[par][a];
+                const int64_t y1 = y + dy, x1 = x + dx;
+                const bool valid = inx && y1 < H && x1 >= 0 && x1 < W;
+                const uint32_t w = tile[(ry + dy) * TC + R + (int)threadIdx.x + dx];
+                acc.pair(pv, Acc::prep(w), valid);
+            }
+            if constexpr (FORM == FORM_MARG) {
+                uint32_t deg = 0;
+                for (int b = 0; b < q.nfull[par]; ++b) {
+                    const int64_t y1 = y + q.fdy[par][b], x1 = x + q.fdx[par][b];
+                    deg += (y1 >= 0 && y1 < H && x1 >= 0 && x1 < W) ? 1u : 0u;
+                }
+                acc.pixel(v, deg, inx);
+            }
+        }
+        __syncthreads();  // before the next tile is staged over this one
+    }
+    flush_image<FORM, CLAMP>(p, lds, bs, im, vmax, mine, q.tiles);
+}
+
+template <typename Pix>
+const void *pick_nbhd_form(int form, bool clamp) {
+    if (form == FORM_TRI)
+        return clamp ? reinterpret_cast<const void *>(nbhd_kernel<Pix, FORM_TRI, true>)
+                     : reinterpret_cast<const void *>(nbhd_kernel<Pix, FORM_TRI, false>);
+    return clamp ? reinterpret_cast<const void *>(nbhd_kernel<Pix, FORM_MARG, true>)
+                 : reinterpret_cast<const void *>(nbhd_kernel<Pix, FORM_MARG, false>);
+}
+
+const void *pick_nbhd_kernel(int dtype, int form, int M) {
+    return dtype == 1 ? pick_nbhd_form<uint8_t>(form, M < 256) : pick_nbhd_form<uint16_t>(form, true);
+}
+
 template <typename Pix, int NB, int K>
 const void *pick_form(int form, bool clamp) {
     if (form == FORM_BAND)
@@ -1737,6 +1870,41 @@ int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int ban
         hipSuccess)
         return 1;
     return n > 0 ? n : 1;
+}
+
+size_t nbhd_lds_layout(NbParams &q, int form, int block) {
+    // the tables (or the finishing step's arrays) first, then the value tile, then the scratch; as
+    // many tile rows as fit (at most 16)
+    const size_t table = lds_main_bytes(form, q.k.M, 1, block, 1);
+    const size_t tile_off = (table + 15) & ~(size_t)15;
+    const size_t row_bytes = (size_t)(block + 2 * q.radius) * sizeof(uint16_t);
+    const size_t room = kMaxLdsBytes - sizeof(BlockScratch) - 16;
+    int rows = 16;
+    while (rows > 1 && tile_off + (size_t)(rows + q.radius) * row_bytes > room) --rows;
+    q.tile_rows = rows;
+    q.tile_off = (uint32_t)tile_off;
+    q.bs_off = (uint32_t)((tile_off + (size_t)(rows + q.radius) * row_bytes + 15) & ~(size_t)15);
+    return (size_t)q.bs_off + sizeof(BlockScratch);
+}
+
+int nbhd_blocks_per_cu(int dtype, int form, int M, int block, size_t lds) {
+    const void *kern = pick_nbhd_kernel(dtype, form, M);
+    if (allow_large_lds(kern) != hipSuccess) return 1;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds) != hipSuccess) return 1;
+    return n > 0 ? n : 1;
+}
+
+hipError_t launch_nbhd(const NbParams &q, int dtype, int form, int block, int grid, size_t lds,
+                       hipStream_t stream) {
+    const void *kern = pick_nbhd_kernel(dtype, form, q.k.M);
+    hipError_t e = allow_large_lds(kern);
+    if (e != hipSuccess) return e;
+    NbParams arg = q;
+    void *args[] = {&arg};
+    e = hipLaunchKernel(kern, dim3(grid), dim3(block), args, lds, stream);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
 }
 
 }  // namespace kohler
