@@ -347,8 +347,10 @@ typedef struct kohler_server_config {
     int32_t max_batch;         /* most requests in one launch (1..slots) */
     int32_t queue_capacity;    /* waiting requests beyond which submit refuses (>= 1) */
     int32_t thr_capacity;      /* thresholds kept per request (0..M) */
-    int32_t use_graphs;        /* nonzero: a request admitted alone replays a per-shape HIP graph */
-    int32_t pad;
+    int32_t use_graphs;        /* nonzero: a request admitted alone replays a per-shape HIP graph
+                                  (not used for requests with labels) */
+    int32_t label_t0;          /* nonzero: video mode, requests may carry a label destination
+                                  (kohler_server_submit_labels) */
     int64_t hbm_budget_bytes;  /* device bytes for slot state plus the image arena (> slot state) */
 } kohler_server_config;
 
@@ -395,6 +397,21 @@ void kohler_server_destroy(kohler_server *srv);
  */
 int kohler_server_submit(kohler_server *srv, const void *img, int64_t H, int64_t W, int64_t pitch,
                          uint64_t *ticket);
+
+/*
+ * Video mode (a server created with label_t0 != 0): as kohler_server_submit, and the launch that
+ * computes the image's curve also segments the image in two classes at its own optimal threshold
+ * t0 (eq (4); the two-class segmentation of the paper's video experiment, Sec. 4): labels[y *
+ * label_pitch + x] = 1 where f(y, x) > t0, else 0, and 0 everywhere when t0 = -1 (the curve is
+ * identically zero: one class). t0 never leaves the device on the way: curve, t0 and labels are one
+ * stream-ordered sequence. `labels` (H rows of label_pitch >= W bytes) is device memory (written
+ * there directly) or host memory (written through a block of the image arena and a copy; pinned
+ * memory keeps the copy asynchronous); it must stay valid until the request completes and holds the
+ * labels once kohler_server_wait returns. Returns as kohler_server_submit, and KOHLER_E_ARG when the
+ * server is not in video mode.
+ */
+int kohler_server_submit_labels(kohler_server *srv, const void *img, int64_t H, int64_t W, int64_t pitch,
+                                uint8_t *labels, int64_t label_pitch, uint64_t *ticket);
 
 /* 1 if the request has completed (or was cancelled), 0 if not yet, KOHLER_E_ARG for an unknown
  * ticket. Never blocks. */

@@ -80,6 +80,22 @@ def _image_args(img):
     return a.ctypes.data, _dtype_code(a.dtype.type), int(H), int(W), int(W), a
 
 
+def _label_args(buf):
+    """(pointer, H, W, pitch, keepalive) of a writable 2-D uint8 destination with unit column stride:
+    a torch tensor (host, pinned or device) or a numpy array, used in place (never copied)."""
+    torch = _torch()
+    if isinstance(buf, torch.Tensor):
+        if buf.dim() != 2 or buf.stride(1) != 1 or buf.dtype != torch.uint8:
+            raise ValueError("labels must be a 2-D uint8 tensor with unit column stride")
+        H, W = buf.shape
+        return buf.data_ptr(), int(H), int(W), int(buf.stride(0) if H > 1 else W), buf
+    a = buf
+    if not isinstance(a, np.ndarray) or a.ndim != 2 or a.dtype != np.uint8 or a.strides[1] != 1 or not a.flags.writeable:
+        raise ValueError("labels must be a writable 2-D uint8 array with unit column stride")
+    H, W = a.shape
+    return a.ctypes.data, int(H), int(W), int(a.strides[0] if H > 1 else W), a
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -382,16 +398,16 @@ class Server:
 
     def __init__(self, ctx: Context, dtype: int = _lib.U8, M: int = 256, nbhd: int = 4,
                  slots: int = 16, lanes: int = 2, max_batch: int = 16, queue_capacity: int = 4096,
-                 thr_capacity: int | None = None, use_graphs: bool = True,
-                 hbm_budget_bytes: int = 1 << 30):
+                 thr_capacity: int | None = None, use_graphs: bool = False,
+                 hbm_budget_bytes: int = 1 << 30, label_t0: bool = False):
         self._lib = _lib.load()
         self.ctx = ctx  # the context must outlive the server
         self.M = int(M)
         self.thr_capacity = self.M if thr_capacity is None else int(thr_capacity)
         self.dtype = int(dtype)
         cfg = ServerConfig(int(dtype), int(M), int(nbhd), int(slots), int(lanes), int(max_batch),
-                           int(queue_capacity), self.thr_capacity, 1 if use_graphs else 0, 0,
-                           int(hbm_budget_bytes))
+                           int(queue_capacity), self.thr_capacity, 1 if use_graphs else 0,
+                           1 if label_t0 else 0, int(hbm_budget_bytes))
         self._h = ctypes.c_void_p()
         st = self._lib.kohler_server_create(ctx._h, ctypes.byref(cfg), ctypes.byref(self._h))
         if st != OK:
@@ -410,18 +426,29 @@ class Server:
         except Exception:
             pass
 
-    def submit(self, img) -> int:
+    def submit(self, img, labels=None) -> int:
         """Queue one image (host array, pinned tensor or device tensor); returns its ticket.
-        Raises KohlerError(E_BUSY) when admission is refused."""
+        Video mode (label_t0=True): `labels`, a uint8 H x W array or tensor (host, pinned or device)
+        with unit column stride, receives the image's two-class segmentation at its own t0 by the
+        time wait() returns. Raises KohlerError(E_BUSY) when admission is refused."""
         ptr, code, H, W, pitch, keep = _image_args(img)
         if code != self.dtype:
             raise TypeError("image dtype does not match the server")
         _complete(img)
         t = ctypes.c_uint64(0)
-        st = self._lib.kohler_server_submit(self._h, ctypes.c_void_p(ptr), H, W, pitch, ctypes.byref(t))
+        if labels is None:
+            st = self._lib.kohler_server_submit(self._h, ctypes.c_void_p(ptr), H, W, pitch, ctypes.byref(t))
+        else:
+            lptr, lH, lW, lpitch, lkeep = _label_args(labels)
+            if (lH, lW) != (H, W):
+                raise ValueError("labels must have the image's shape")
+            _complete(labels)
+            keep = (keep, lkeep)
+            st = self._lib.kohler_server_submit_labels(self._h, ctypes.c_void_p(ptr), H, W, pitch,
+                                                       ctypes.c_void_p(lptr), lpitch, ctypes.byref(t))
         if st != OK:
             raise KohlerError(st, "kohler_server_submit")
-        self._keep[t.value] = keep  # the image must stay alive until the request completes
+        self._keep[t.value] = keep  # the image (and labels) must stay alive until the request completes
         return int(t.value)
 
     def poll(self, ticket: int) -> bool:

@@ -16,7 +16,8 @@ EXPORTS = (
     "kohler_create", "kohler_destroy", "kohler_strerror", "kohler_curve", "kohler_curve_async",
     "kohler_curve_batch", "kohler_curve_noalloc", "kohler_curve_nbhd_async", "kohler_set_plan", "kohler_get_plan", "kohler_autotune", "kohler_segment",
     "kohler_class_stats", "kohler_mean_image", "kohler_top_thresholds",
-    "kohler_server_create", "kohler_server_destroy", "kohler_server_submit", "kohler_server_poll",
+    "kohler_server_create", "kohler_server_destroy", "kohler_server_submit", "kohler_server_submit_labels",
+    "kohler_server_poll",
     "kohler_server_wait", "kohler_server_cancel", "kohler_server_pause", "kohler_server_stats",
 )
 
@@ -45,7 +46,7 @@ class ServerConfig(_Struct):
     _fields_ = [("dtype", ctypes.c_int32), ("M", ctypes.c_int32), ("nbhd", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("lanes", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("thr_capacity", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32), ("label_t0", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64)]
 
 
@@ -123,6 +124,8 @@ def load(path: str = LIB_PATH):
     lib.kohler_server_destroy.restype = None
     lib.kohler_server_submit.argtypes = [vp, vp, i64, i64, i64, ctypes.POINTER(u64)]
     lib.kohler_server_submit.restype = ctypes.c_int
+    lib.kohler_server_submit_labels.argtypes = [vp, vp, i64, i64, i64, vp, i64, ctypes.POINTER(u64)]
+    lib.kohler_server_submit_labels.restype = ctypes.c_int
     lib.kohler_server_poll.argtypes = [vp, u64]
     lib.kohler_server_poll.restype = ctypes.c_int
     lib.kohler_server_wait.argtypes = [vp, u64, vp, vp, vp, vp, i32, ctypes.POINTER(RequestInfo)]

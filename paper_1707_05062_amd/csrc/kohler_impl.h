@@ -161,6 +161,24 @@ int nbhd_blocks_per_cu(int dtype, int form, int M, int block, size_t lds);
 hipError_t launch_nbhd(const NbParams &q, int dtype, int form, int block, int grid, size_t lds,
                        hipStream_t stream);
 
+// ------------------------------------------------------------------------------------------------
+// Two-class segmentation at a device-resident t0 (the serving loop's video mode, eq (4)): label 1
+// where f > t0, else 0; every pixel 0 when t0 < 0 (the curve is identically zero: one class).
+
+struct LabelJob {
+    const void *img;       // H rows of `pitch` elements of the launch's dtype (device)
+    uint8_t *labels;       // H rows of `lpitch` bytes (device)
+    const int32_t *t0;     // device
+    int64_t H, W, pitch, lpitch;
+};
+constexpr int kMaxLabelJobs = 16;
+struct LabelJobs {
+    LabelJob job[kMaxLabelJobs];
+    int32_t n, dtype;
+};
+// One launch labelling js.n images (1..kMaxLabelJobs). Returns hipSuccess or the launch error.
+hipError_t launch_label_t0(const LabelJobs &js, hipStream_t stream);
+
 // Launch the curve kernel (p.band and p.copies already set). Returns hipSuccess or the launch error.
 hipError_t launch_curve(const KParams &p, int dtype, int nbhd, int form, int px_per_lane, int block,
                         int grid, hipStream_t stream);

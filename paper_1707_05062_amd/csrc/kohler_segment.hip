@@ -327,7 +327,40 @@ const void *seg_kernel_for(int dtype, int label_dtype) {
                                     : reinterpret_cast<const void *>(segment_kernel<uint16_t, uint16_t>);
 }
 
+// Two classes at the image's own t0 (read from device memory): blockIdx.y picks the image; each
+// lane labels 4 consecutive pixels of a row per step, the workgroups striding over the rows.
+template <typename Pin>
+__global__ void __launch_bounds__(kSegBlock) label_t0_kernel(LabelJobs js) {
+    const LabelJob &jb = js.job[blockIdx.y];
+    const int32_t t0 = *(const KOHLER_SEG_GLOBAL int32_t *)jb.t0;
+    const int64_t quads = (jb.W + 3) / 4;
+    const int64_t total = jb.H * quads;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t y = q / quads, x0 = (q - y * quads) * 4;
+        const KOHLER_SEG_GLOBAL Pin *row = (const KOHLER_SEG_GLOBAL Pin *)(static_cast<const Pin *>(jb.img) + y * jb.pitch);
+        KOHLER_SEG_GLOBAL uint8_t *out = (KOHLER_SEG_GLOBAL uint8_t *)(jb.labels + y * jb.lpitch);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (x0 + k < jb.W) out[x0 + k] = (t0 >= 0 && (int32_t)row[x0 + k] > t0) ? 1 : 0;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_label_t0(const LabelJobs &js, hipStream_t stream) {
+    if (js.n < 1 || js.n > kMaxLabelJobs) return hipErrorInvalidValue;
+    int64_t most = 1;
+    for (int i = 0; i < js.n; ++i) most = std::max<int64_t>(most, js.job[i].H * ((js.job[i].W + 3) / 4));
+    const int gx = (int)std::min<int64_t>((most + kSegBlock - 1) / kSegBlock, 1024);
+    LabelJobs arg = js;
+    void *args[] = {&arg};
+    const void *kern = js.dtype == KOHLER_U8 ? reinterpret_cast<const void *>(label_t0_kernel<uint8_t>)
+                                             : reinterpret_cast<const void *>(label_t0_kernel<uint16_t>);
+    hipError_t e = hipLaunchKernel(kern, dim3(gx, js.n), dim3(kSegBlock), args, 0, stream);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 }  // namespace kohler
 
 using namespace kohler;

@@ -108,6 +108,12 @@ struct Request {
     std::vector<int64_t> sum, count;
     std::vector<double> C;
     std::vector<int32_t> thr;
+    // video mode: where the labels go, and the arena block they pass through for a host destination
+    uint8_t *labels = nullptr;
+    int64_t lpitch = 0;
+    bool labels_on_device = false;
+    bool has_label_block = false;
+    size_t label_off = 0;
 };
 
 // What a launch needs of one admitted request (copied out of the request table before the
@@ -120,6 +126,10 @@ struct Item {
     size_t bytes;
     int slot;
     size_t arena_off;
+    uint8_t *labels;       // destination of the labels (video mode), or null
+    int64_t lpitch;
+    bool labels_on_device;
+    size_t label_off;      // arena block the labels pass through (host destination)
 };
 
 struct Launch {
@@ -228,6 +238,43 @@ GraphKey graph_key(const Item &it, int lane, const kohler_plan &pl) {
                     pl.px_per_lane, pl.replicas, pl.copies, pl.acc_split);
 }
 
+// Video mode: after the curve launch on the same stream, the labels of every item that asked for
+// them (t0 read from the slot's device record), written to the destination or to the item's arena
+// block and copied from there.
+hipError_t issue_labels(kohler_server *s, const std::vector<Item> &items, hipStream_t stream) {
+    LabelJobs js{};
+    js.dtype = s->cfg.dtype;
+    auto flush = [&]() -> hipError_t {
+        if (js.n == 0) return hipSuccess;
+        hipError_t e = launch_label_t0(js, stream);
+        js.n = 0;
+        return e;
+    };
+    for (const Item &it : items) {
+        if (!it.labels) continue;
+        LabelJob &j = js.job[js.n++];
+        j.img = device_image(s, it);
+        j.labels = it.labels_on_device ? it.labels : s->arena_base + it.label_off;
+        j.t0 = reinterpret_cast<const int32_t *>(s->rec_dev + (size_t)it.slot * s->rec_bytes + s->off_int) + 1;
+        j.H = it.H;
+        j.W = it.W;
+        j.pitch = it.pitch;
+        j.lpitch = it.labels_on_device ? it.lpitch : it.W;
+        if (js.n == kMaxLabelJobs) {
+            hipError_t e = flush();
+            if (e != hipSuccess) return e;
+        }
+    }
+    hipError_t e = flush();
+    for (const Item &it : items) {
+        if (e != hipSuccess) break;
+        if (it.labels && !it.labels_on_device)
+            e = hipMemcpy2DAsync(it.labels, (size_t)it.lpitch, s->arena_base + it.label_off, (size_t)it.W,
+                                 (size_t)it.W, (size_t)it.H, hipMemcpyDeviceToHost, stream);
+    }
+    return e;
+}
+
 // Issue one launch (copies in, kernel, copies out, event) on `lane`. Runs without the lock.
 int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L) {
     const kohler_server_config &c = s->cfg;
@@ -246,7 +293,8 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
     p.total_units = units;
     hipError_t e = hipSuccess;
 
-    if (n == 1 && c.use_graphs && (s->graphs.size() < kMaxGraphs ||
+    const bool labelled = std::any_of(items.begin(), items.end(), [](const Item &it) { return it.labels != nullptr; });
+    if (n == 1 && c.use_graphs && !labelled && (s->graphs.size() < kMaxGraphs ||
                                    s->graphs.count(graph_key(items[0], lane, pl)))) {
         const Item &it = items[0];
         p.n = 1;
@@ -357,6 +405,7 @@ int issue(kohler_server *s, int lane, const std::vector<Item> &items, Launch &L)
         if ((e = launch_curve(p, c.dtype, c.nbhd, pl.form, pl.px_per_lane, pl.block, pl.grid, stream)) !=
             hipSuccess)
             return pick_status(e);
+        if (labelled && (e = issue_labels(s, items, stream)) != hipSuccess) return pick_status(e);
         for (const Item &it : items)
             if ((e = hipMemcpyAsync(s->rec_host + (size_t)it.slot * s->rec_bytes,
                                     s->rec_dev + (size_t)it.slot * s->rec_bytes, s->rec_bytes,
@@ -392,6 +441,10 @@ void retire(kohler_server *s, Request &r, int status) {
     if (r.has_arena) {
         s->arena.release(r.arena_off, r.bytes);
         r.has_arena = false;
+    }
+    if (r.has_label_block) {
+        s->arena.release(r.label_off, (size_t)(r.H * r.W));
+        r.has_label_block = false;
     }
     if (r.staging) {
         s->staging_pool.emplace(r.staging_bytes, r.staging);
@@ -443,17 +496,27 @@ bool admit(kohler_server *s, std::unique_lock<std::mutex> &lk) {
         while (!s->queue.empty() && (int)items.size() < s->cfg.max_batch && !s->free_slots.empty()) {
             const uint64_t t = s->queue.front();
             Request &r = s->reqs.at(t);
-            size_t off = 0;
-            if (!r.on_device) {
-                if (!s->arena.alloc(r.bytes, &off)) break;  // head waits for arena room
+            size_t off = 0, loff = 0;
+            const bool need_img = !r.on_device, need_lab = r.labels && !r.labels_on_device;
+            if (need_img && !s->arena.alloc(r.bytes, &off)) break;  // head waits for arena room
+            if (need_lab && !s->arena.alloc((size_t)(r.H * r.W), &loff)) {
+                if (need_img) s->arena.release(off, r.bytes);
+                break;
+            }
+            if (need_img) {
                 r.has_arena = true;
                 r.arena_off = off;
+            }
+            if (need_lab) {
+                r.has_label_block = true;
+                r.label_off = loff;
             }
             r.slot = s->free_slots.back();
             s->free_slots.pop_back();
             r.state = RUNNING;
             r.t_launch = now_ns();
-            items.push_back(Item{t, r.img, r.on_device, r.H, r.W, r.pitch, r.bytes, r.slot, r.arena_off});
+            items.push_back(Item{t, r.img, r.on_device, r.H, r.W, r.pitch, r.bytes, r.slot, r.arena_off, r.labels,
+                                 r.lpitch, r.labels_on_device, r.label_off});
             s->queue.pop_front();
         }
         if (items.empty()) break;  // no slot or no arena room for the head request
@@ -646,12 +709,25 @@ void kohler_server_destroy(kohler_server *s) {
     free_all(s);
 }
 
-int kohler_server_submit(kohler_server *s, const void *img, int64_t H, int64_t W, int64_t pitch,
-                         uint64_t *ticket) {
+// Both submit entry points: queue one request, with a label destination (video mode) or without.
+static int submit_request(kohler_server *s, const void *img, int64_t H, int64_t W, int64_t pitch, uint8_t *labels,
+                          int64_t lpitch, uint64_t *ticket) {
     if (!s || !img || !ticket) return KOHLER_E_ARG;
     const kohler_server_config &c = s->cfg;
     if (!valid_shape(c.dtype, H, W, pitch, c.M, c.nbhd)) return KOHLER_E_ARG;
     const size_t bytes = ((size_t)(H - 1) * (size_t)pitch + (size_t)W) * s->esz;
+    bool labels_on_device = false;
+    if (labels) {
+        if (!c.label_t0 || lpitch < W) return KOHLER_E_ARG;
+        hipPointerAttribute_t la;
+        labels_on_device = hipPointerGetAttributes(&la, labels) == hipSuccess && la.type == hipMemoryTypeDevice;
+        (void)hipGetLastError();
+        if (!labels_on_device && round_up((size_t)(H * W), kAlign) > s->arena.capacity()) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->st.refused++;
+            return KOHLER_E_BUSY;
+        }
+    }
 
     hipPointerAttribute_t attr;
     bool on_device = false, pinned = false;
@@ -660,7 +736,9 @@ int kohler_server_submit(kohler_server *s, const void *img, int64_t H, int64_t W
         pinned = attr.type == hipMemoryTypeHost;
     }
     (void)hipGetLastError();
-    if (!on_device && round_up(bytes, kAlign) > s->arena.capacity()) {
+    const size_t arena_need = (on_device ? 0 : round_up(bytes, kAlign)) +
+                              (labels && !labels_on_device ? round_up((size_t)(H * W), kAlign) : 0);
+    if (arena_need > s->arena.capacity()) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->st.refused++;
         return KOHLER_E_BUSY;
@@ -706,6 +784,9 @@ int kohler_server_submit(kohler_server *s, const void *img, int64_t H, int64_t W
         r.W = W;
         r.pitch = pitch;
         r.bytes = bytes;
+        r.labels = labels;
+        r.lpitch = lpitch;
+        r.labels_on_device = labels_on_device;
         r.t_submit = now_ns();
         s->queue.push_back(t);
         s->st.submitted++;
@@ -713,6 +794,17 @@ int kohler_server_submit(kohler_server *s, const void *img, int64_t H, int64_t W
     }
     s->cv_sched.notify_one();
     return KOHLER_OK;
+}
+
+int kohler_server_submit(kohler_server *s, const void *img, int64_t H, int64_t W, int64_t pitch,
+                         uint64_t *ticket) {
+    return submit_request(s, img, H, W, pitch, nullptr, 0, ticket);
+}
+
+int kohler_server_submit_labels(kohler_server *s, const void *img, int64_t H, int64_t W, int64_t pitch,
+                                uint8_t *labels, int64_t label_pitch, uint64_t *ticket) {
+    if (!labels) return KOHLER_E_ARG;
+    return submit_request(s, img, H, W, pitch, labels, label_pitch, ticket);
 }
 
 int kohler_server_poll(kohler_server *s, uint64_t ticket) {

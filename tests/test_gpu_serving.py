@@ -66,7 +66,7 @@ def test_alone_and_in_the_mix(K, ctx):
     plain = [ctx.curve(im, M, 4) for im in imgs]
     for i in (0, 1, 2, 3, 7):  # oracle on the cheap ones
         assert_result(plain[i], reference(imgs[i], M, 4), what=f"plain {imgs[i].shape}")
-    srv = K.Server(ctx, M=M, nbhd=4, slots=8, lanes=2, max_batch=8, hbm_budget_bytes=256 << 20)
+    srv = K.Server(ctx, M=M, nbhd=4, slots=8, lanes=2, max_batch=8, hbm_budget_bytes=256 << 20, use_graphs=True)
     try:
         # alone: one request at a time (graph replays)
         alone = []
@@ -98,7 +98,7 @@ def test_alone_and_in_the_mix(K, ctx):
 def test_graph_replays_with_eager_work_between(K, ctx):
     """One shape replayed many times with different contents, eager context calls in between:
     every replay must equal the eager result of the same image."""
-    srv = K.Server(ctx, M=M, nbhd=4, slots=2, lanes=1, max_batch=1, hbm_budget_bytes=64 << 20)
+    srv = K.Server(ctx, M=M, nbhd=4, slots=2, lanes=1, max_batch=1, hbm_budget_bytes=64 << 20, use_graphs=True)
     try:
         for k in range(6):
             img = gen.random_image(np.random.default_rng(900 + k), 300, 700, M, np.uint8, "smooth" if k % 2 else "uniform").astype(np.uint8)
@@ -212,3 +212,80 @@ def test_tuned_plan_cache(K, ctx, tmp_path):
         assert not hit1 and hit2 and p1 == p2 and us1 == us2
     finally:
         c2.close()
+
+
+# ----------------------------------------------------------------------------------------------
+# video mode: each frame segmented in two classes at its own t0 (eq (4); Sec. 4's video experiment)
+
+def two_class(img, t0):
+    """The oracle's labels at one threshold (class = number of thresholds below the value), one
+    class when the curve is identically zero (t0 = -1)."""
+    import oracle
+    return oracle.segment(img, [t0] if t0 >= 0 else []).astype(np.uint8)
+
+
+def label_buffer(H, W, kind, wide=0):
+    import torch
+    if kind == "pageable":
+        return np.full((H, W + wide), 7, np.uint8)[:, :W]
+    t = torch.full((H, W + wide), 7, dtype=torch.uint8)
+    t = t.pin_memory() if kind == "pinned" else t.cuda()
+    return t[:, :W]
+
+
+def labels_np(buf):
+    import torch
+    return buf.cpu().numpy() if isinstance(buf, torch.Tensor) else np.asarray(buf)
+
+
+def video_frames():
+    pool = gen.serve_pool(n1080=4, n4k=0, n18=0)
+    frames = list(pool["1080p"]) + mixed_images()[:6]
+    frames.append(np.full((40, 70), 9, np.uint8))  # constant: C identically zero, t0 = -1
+    return frames
+
+
+def test_video_t0_labels_alone_and_in_the_mix(K, ctx):
+    import torch
+    frames = video_frames()
+    refs = [reference(f, M, 4, exact_all=f.size <= 3_000_000) for f in frames]
+    want = [two_class(f, r["t0"]) for f, r in zip(frames, refs)]
+    assert refs[-1]["t0"] == -1 and not want[-1].any()
+    img_kinds = ["pinned", "pageable", "device"]
+    lab_kinds = ["device", "pinned", "pageable"]
+    for cfg in (dict(slots=1, lanes=1, max_batch=1), dict(slots=8, lanes=2, max_batch=8)):
+        srv = K.Server(ctx, M=M, nbhd=4, hbm_budget_bytes=256 << 20, label_t0=True, **cfg)
+        try:
+            for rnd in range(2):
+                bufs = [label_buffer(*f.shape, lab_kinds[(i + rnd) % 3], wide=3 * (i % 2)) for i, f in enumerate(frames)]
+                srcs = [as_kind(f, img_kinds[(i + rnd) % 3]) for i, f in enumerate(frames)]
+                if cfg["max_batch"] > 1:
+                    srv.pause(True)
+                tickets = [srv.submit(src, labels=b) for src, b in zip(srcs, bufs)]
+                if cfg["max_batch"] > 1:
+                    srv.pause(False)
+                results = [srv.wait(t) for t in tickets]
+                torch.cuda.synchronize()
+                if cfg["max_batch"] > 1:
+                    assert max(info["batch"] for _, info in results) > 1
+                for i, ((res, info), b) in enumerate(zip(results, bufs)):
+                    what = f"{cfg} round {rnd} frame {i} {frames[i].shape} labels {lab_kinds[(i + rnd) % 3]}"
+                    assert_result(res, refs[i], what=what)
+                    assert info["graph"] == 0
+                    got = labels_np(b)
+                    assert np.array_equal(got, want[i]), what
+            say("video mode", cfg, srv.stats())
+        finally:
+            srv.close()
+
+
+def test_video_mode_requires_label_t0(K, ctx):
+    srv = K.Server(ctx, M=M, nbhd=4, slots=2, lanes=1, max_batch=1, hbm_budget_bytes=64 << 20)
+    try:
+        f = np.zeros((8, 8), np.uint8)
+        with pytest.raises(K.KohlerError):
+            srv.submit(f, labels=np.zeros((8, 8), np.uint8))
+        res, _ = srv.wait(srv.submit(f))  # the server still serves curves
+        assert res.t0 == -1
+    finally:
+        srv.close()
