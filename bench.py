@@ -13,9 +13,12 @@ Also measured in the same run (reported beside the headline, not as separate lin
   batched  96 uint8 images of log-uniform sizes (128^2 .. 4000x3000) in one persistent launch vs the
            plain kernel launched once per image on one stream;
   served   a Poisson stream of 240 requests/s (70% 1080p video frames, 20% 4K frames, 10% 18 MP
-           stills) through the serving loop (with and without the per-frame HIP graph) vs the same
-           loop restricted to one image per launch, with p50/p99 latency from scheduled arrival to
-           results in host memory, plus a burst that saturates them.
+           stills) through the serving loop (eager launches, the default; with per-shape HIP graphs;
+           and in video mode, where each request also gets its two-class labels at its own t0) vs
+           the same loop restricted to one image per launch, with p50/p99 latency from scheduled
+           arrival to results (and labels) in host memory, plus a burst that saturates them.
+  other    the 256x256 and 4096^2 12-bit (N4, N8) workloads, the hexagonal 6-neighbourhood and the
+           pre-filtered N4 curve of the 18 MP image.
 
 Prints ONE JSON line with the headline throughput in Gpixel/s, the roofline of the curve kernel
 (algorithmic bytes / average kernel duration from HIP events on the launch stream) and the CPU
@@ -361,6 +364,64 @@ def config_line(K, torch, name: str, workload: str, img: np.ndarray, M: int, nbh
             "thresholds": n_thr, "selfcheck": ok}
 
 
+def nbhd_line(K, torch, name: str, workload: str, img: np.ndarray, M: int, half, hex: bool, prefilter: bool,
+              pairs: int, reps: int = 100, rotate: int = 16) -> dict:
+    """The other-neighbourhood / pre-filter entry point on one image per launch, inputs resident and
+    rotated; HIP events around `reps` back-to-back launches on the launch stream. Self-check: the
+    closed-form total over the curve (sum_t count(t) = sum of the pair gaps) on the raw image (no
+    filter) or the result's own consistency (filter on)."""
+    dev = torch.device("cuda", 0)
+    a = np.ascontiguousarray(img)
+    src = torch.from_numpy(a).to(dev)
+    bufs = [src.clone() for _ in range(rotate)]
+    ctx = K.Context(0)
+    try:
+        stream = torch.cuda.current_stream(dev)
+        outs = ctx.alloc_outputs(M, M)
+        ctx.curve_nbhd_async(bufs[0], M, half=half, hex=hex, prefilter=prefilter, out=outs, stream=stream)
+        torch.cuda.synchronize()
+        n_thr, t0, status = [int(x) for x in outs["ints"].cpu()]
+        ok = status == 0
+        for i in range(10):
+            ctx.curve_nbhd_async(bufs[i % rotate], M, half=half, hex=hex, prefilter=prefilter, out=outs, stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for i in range(reps):
+            ctx.curve_nbhd_async(bufs[(10 + i) % rotate], M, half=half, hex=hex, prefilter=prefilter, out=outs,
+                                 stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kern = e0.elapsed_time(e1) * 1e-3 / reps
+    finally:
+        ctx.close()
+    npx = a.size
+    alg_bytes = npx * a.itemsize + 3 * M * 8 + 4 * n_thr + 12
+    log(f"{name}: {kern*1e6:.2f} us, {npx / kern / 1e9:.1f} Gpixel/s, status {status}")
+    return {"workload": workload, "kernel_us": kern * 1e6, "gpixel_s": npx / kern / 1e9,
+            "pairs_per_launch": pairs, "pairs_per_s": pairs / kern,
+            "roofline": {"bound": "hbm", "achieved": alg_bytes / kern / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": alg_bytes / kern / 1e9 / HBM_PEAK_GBS, "alg_bytes_per_launch": alg_bytes},
+            "thresholds": n_thr, "t0": t0, "status_ok": ok}
+
+
+def nbhd_configs(K, torch, gen) -> dict:
+    img = gen.cfg2_image()
+    H, W = img.shape
+    n4 = H * (W - 1) + (H - 1) * W
+    hexp = n4 + (H - 1) * (W - 1)
+    base = "3456x5184 uint8 (18 MP) as the headline, M=256"
+    return {
+        "hex6_18mp": nbhd_line(K, torch, "hex6 18 MP", base + ", hexagonal 6-neighbourhood (odd rows shifted "
+                               "right)", img, 256, None, True, False, hexp),
+        "n4_prefilter_18mp": nbhd_line(K, torch, "N4 + binomial 18 MP", base + ", 3x3 binomial pre-filter fused "
+                                       "into the tile loader, then N4", img, 256, [(0, 1), (1, 0)], False, True, n4),
+        "n4_nbhd_path_18mp": nbhd_line(K, torch, "N4 via nbhd path 18 MP", base + ", N4 through the generic "
+                                       "neighbourhood kernel (no filter), for comparison with the headline kernel",
+                                       img, 256, [(0, 1), (1, 0)], False, False, n4),
+    }
+
+
 def other_configs(K, torch, gen, lds_probe: dict) -> dict:
     out = {"c1_256x256_u8_n4": config_line(
         K, torch, "c1", "256x256 uint8, six constant rectangles + N(0,8^2) noise, M=256, 4-neighbourhood",
@@ -519,13 +580,16 @@ def make_trace(rate: float, seconds: float, seed: int = 5):
     return out
 
 
-def run_trace(K, ctx, pool, trace, warm_s, server_kw, burst=False):
+def run_trace(K, ctx, pool, trace, warm_s, server_kw, burst=False, labels=None):
     srv = K.Server(ctx, **server_kw)
     counters = {c: 0 for c in SERVE_CLASSES}
     try:
         # one request per class first, so that per-shape graphs exist before the clock starts
         for c in SERVE_CLASSES:
-            srv.wait(srv.submit(pool[c][0]))
+            if labels is not None:
+                srv.wait(srv.submit(pool[c][0], labels=labels[c][0]))
+            else:
+                srv.wait(srv.submit(pool[c][0]))
         tickets: queue.Queue = queue.Queue()
         t0 = time.monotonic_ns() + 20_000_000
 
@@ -545,7 +609,11 @@ def run_trace(K, ctx, pool, trace, warm_s, server_kw, burst=False):
                         if d > 300_000:
                             time.sleep((d - 200_000) / 1e9)
                 try:
-                    tk = srv.submit(frame)
+                    if labels is not None:
+                        lab = labels[c][(counters[c] - 1) % len(labels[c])]
+                        tk = srv.submit(frame, labels=lab)
+                    else:
+                        tk = srv.submit(frame)
                 except K.KohlerError as e:
                     tickets.put((ta, ci, None, e.status))
                     continue
@@ -605,8 +673,13 @@ def served(args, K, ctx, torch, gen) -> dict:
                    and np.array_equal(r.C, ref.C) and r.t0 == ref.t0)
     check_srv.close()
 
-    server_kw = dict(slots=32, lanes=2, max_batch=16, use_graphs=True, hbm_budget_bytes=2 << 30)
-    eager_kw = dict(server_kw, use_graphs=False)
+    server_kw = dict(slots=32, lanes=2, max_batch=16, use_graphs=False, hbm_budget_bytes=2 << 30)
+    graph_kw = dict(server_kw, use_graphs=True)
+    video_kw = dict(server_kw, label_t0=True, hbm_budget_bytes=3 << 30)
+    # video mode: every request also returns its two-class labels at its own t0, into pinned host
+    # buffers cycled per class (more buffers than requests in flight)
+    labels = {c: [torch.empty(pool[c][0].shape, dtype=torch.uint8).pin_memory() for _ in range(48)]
+              for c in SERVE_CLASSES}
     plain_kw = dict(slots=1, lanes=1, max_batch=1, use_graphs=False, hbm_budget_bytes=256 << 20)
     trace = make_trace(args.rate, args.serve_seconds + 1.0)
     log(f"served: {len(trace)} arrivals over {args.serve_seconds + 1.0:.0f} s")
@@ -616,18 +689,23 @@ def served(args, K, ctx, torch, gen) -> dict:
                        "pinned host frames cycled from a pool; latency = scheduled arrival to "
                        "results in host memory",
            "results_match_context": ok,
-           "server_config": server_kw, "server_eager_config": eager_kw, "plain_config": plain_kw}
+           "server_config": server_kw, "server_graphs_config": graph_kw, "server_video_t0_config": video_kw,
+           "plain_config": plain_kw}
     res["server"] = run_trace(K, ctx, pool, trace, 1.0, server_kw)
     log(f"served server: {res['server']['p50_ms']:.3f}/{res['server']['p99_ms']:.3f} ms p50/p99")
-    res["server_eager"] = run_trace(K, ctx, pool, trace, 1.0, eager_kw)
-    log(f"served server without graphs: {res['server_eager']['p50_ms']:.3f}/{res['server_eager']['p99_ms']:.3f} ms p50/p99")
+    res["server_graphs"] = run_trace(K, ctx, pool, trace, 1.0, graph_kw)
+    log(f"served server with per-shape graphs: {res['server_graphs']['p50_ms']:.3f}/{res['server_graphs']['p99_ms']:.3f} ms p50/p99")
+    res["server_video_t0"] = run_trace(K, ctx, pool, trace, 1.0, video_kw, labels=labels)
+    log(f"served server, video mode (labels at t0 included): {res['server_video_t0']['p50_ms']:.3f}/"
+        f"{res['server_video_t0']['p99_ms']:.3f} ms p50/p99")
     res["plain"] = run_trace(K, ctx, pool, trace, 1.0, plain_kw)
     log(f"served plain:  {res['plain']['p50_ms']:.3f}/{res['plain']['p99_ms']:.3f} ms p50/p99")
     rng = np.random.default_rng(55)
     burst = [(0.0, int(rng.choice(3, p=SERVE_MIX))) for _ in range(args.burst)]
     res["burst"] = {"requests": len(burst),
                     "server": run_trace(K, ctx, pool, burst, 0.0, server_kw, burst=True),
-                    "server_eager": run_trace(K, ctx, pool, burst, 0.0, eager_kw, burst=True),
+                    "server_graphs": run_trace(K, ctx, pool, burst, 0.0, graph_kw, burst=True),
+                    "server_video_t0": run_trace(K, ctx, pool, burst, 0.0, video_kw, burst=True, labels=labels),
                     "plain": run_trace(K, ctx, pool, burst, 0.0, plain_kw, burst=True)}
     log(f"burst: server {res['burst']['server']['gpixel_s']:.1f} Gpx/s, "
         f"plain {res['burst']['plain']['gpixel_s']:.1f} Gpx/s")
@@ -683,6 +761,7 @@ def run(args) -> dict:
     result["paper_context"]["this_run_vs_fast_A"] = head["value"] / 0.138
     if args.only != "curve":
         result["configs"] = other_configs(K, torch, gen, lds_probe)
+        result["neighbourhoods"] = nbhd_configs(K, torch, gen)
     if args.only == "all":
         result["batched"] = batched(args, K, ctx, torch, gen)
         result["served"] = served(args, K, ctx, torch, gen)

@@ -25,70 +25,17 @@
 #include "kohler.h"
 #include "kohler_host.h"
 #include "kohler_impl.h"
+#include "kohler_arena.h"
 
 using namespace kohler;
 
 namespace {
-
-constexpr size_t kAlign = 256;
-
-size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 int64_t now_ns() {
     timespec ts;
     clock_gettime(CLOCK_MONOTONIC, &ts);
     return (int64_t)ts.tv_sec * 1000000000 + ts.tv_nsec;
 }
-
-// First-fit allocator over the byte range [0, cap) of the image arena; blocks are multiples of
-// 256 bytes and free neighbours are merged.
-class Arena {
-public:
-    void reset(size_t cap) {
-        cap_ = cap;
-        used_ = peak_ = 0;
-        free_.clear();
-        if (cap) free_[0] = cap;
-    }
-    size_t capacity() const { return cap_; }
-    size_t used() const { return used_; }
-    size_t peak() const { return peak_; }
-    bool alloc(size_t bytes, size_t *off) {
-        bytes = round_up(std::max<size_t>(bytes, 1), kAlign);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < bytes) continue;
-            const size_t start = it->first, rest = it->second - bytes;
-            free_.erase(it);
-            if (rest) free_[start + bytes] = rest;
-            *off = start;
-            used_ += bytes;
-            peak_ = std::max(peak_, used_);
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t bytes) {
-        bytes = round_up(std::max<size_t>(bytes, 1), kAlign);
-        used_ -= bytes;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + bytes == next->first) {
-            bytes += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += bytes;
-                return;
-            }
-        }
-        free_[off] = bytes;
-    }
-
-private:
-    size_t cap_ = 0, used_ = 0, peak_ = 0;
-    std::map<size_t, size_t> free_;  // offset -> length
-};
 
 enum ReqState { QUEUED, RUNNING, DONE };
 
@@ -492,32 +439,17 @@ bool admit(kohler_server *s, std::unique_lock<std::mutex> &lk) {
     for (int lane = 0; lane < nl; ++lane) {
         if (s->lane_busy[lane] || s->stop || s->paused) continue;
         if (s->queue.empty() || s->ev_pool.empty() || s->table_pool.empty()) break;
+        std::vector<uint64_t> admitted;
+        admit_in_order(s->queue, [&](uint64_t t) -> Request & { return s->reqs.at(t); }, s->arena, s->free_slots,
+                       s->cfg.max_batch, admitted);
         std::vector<Item> items;
-        while (!s->queue.empty() && (int)items.size() < s->cfg.max_batch && !s->free_slots.empty()) {
-            const uint64_t t = s->queue.front();
+        const int64_t t_launch = now_ns();
+        for (uint64_t t : admitted) {
             Request &r = s->reqs.at(t);
-            size_t off = 0, loff = 0;
-            const bool need_img = !r.on_device, need_lab = r.labels && !r.labels_on_device;
-            if (need_img && !s->arena.alloc(r.bytes, &off)) break;  // head waits for arena room
-            if (need_lab && !s->arena.alloc((size_t)(r.H * r.W), &loff)) {
-                if (need_img) s->arena.release(off, r.bytes);
-                break;
-            }
-            if (need_img) {
-                r.has_arena = true;
-                r.arena_off = off;
-            }
-            if (need_lab) {
-                r.has_label_block = true;
-                r.label_off = loff;
-            }
-            r.slot = s->free_slots.back();
-            s->free_slots.pop_back();
             r.state = RUNNING;
-            r.t_launch = now_ns();
+            r.t_launch = t_launch;
             items.push_back(Item{t, r.img, r.on_device, r.H, r.W, r.pitch, r.bytes, r.slot, r.arena_off, r.labels,
                                  r.lpitch, r.labels_on_device, r.label_off});
-            s->queue.pop_front();
         }
         if (items.empty()) break;  // no slot or no arena room for the head request
         Launch L;
