@@ -31,7 +31,13 @@
  *   - Arguments are checked before any device work. A bad argument returns KOHLER_E_ARG and leaves
  *     every output untouched.
  *   - A pixel value >= M is detected on the device; the call then reports KOHLER_E_RANGE and the
- *     outputs are unspecified (no memory outside the documented buffers is touched).
+ *     outputs are unspecified (no memory outside the documented buffers is touched). This is the
+ *     rule of every entry point that computes a curve. The consumers of thresholds already
+ *     computed (kohler_segment, kohler_class_stats, kohler_mean_image) follow a different rule on
+ *     purpose: they must give every pixel a class and have no device status word, so a value >= M
+ *     is placed in the top class (it lies above every threshold), counted at the value M. Chained
+ *     after a curve call on the same image, they inherit that call's KOHLER_E_RANGE, which the
+ *     caller checks before trusting either.
  *   - More local maxima than thr_capacity: the first thr_capacity are written, *n_thresholds gets
  *     the full number, and the status is KOHLER_E_CAPACITY (sum, count, C and t0 are still valid).
  *   - The caller owns every input and output buffer. A context owns its device scratch; nothing is

@@ -24,7 +24,7 @@ ROOFLINE_LIB = os.path.join(PKG, "libkohler_roofline.so")
 ROOFLINE_SOURCE = "kohler_roofline.hip"
 
 SOURCES = ["kohler_kernels.hip", "kohler_api.cpp", "kohler_server.cpp", "kohler_segment.hip", "kohler_noalloc.hip"]
-HEADERS = ["kohler_impl.h", "kohler_host.h", "kohler_arena.h"]
+HEADERS = ["kohler_impl.h", "kohler_host.h", "kohler_arena.h", "kohler_columns.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

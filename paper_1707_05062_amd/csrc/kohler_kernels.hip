@@ -35,6 +35,7 @@
 #include <type_traits>
 
 #include "kohler_impl.h"
+#include "kohler_columns.h"
 
 namespace kohler {
 namespace {
@@ -269,7 +270,7 @@ __device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<
     if constexpr (PACKED) {
         // the last strip of a row is packed only when W is a multiple of K: lanes past the row
         // end re-read the row's last aligned chunk, and their pairs are masked out
-        const uint32_t cv = (uint32_t)(FULL ? c : min(c, W - K));
+        const uint32_t cv = (uint32_t)packed_column(c, K, W, FULL);
         if constexpr (NW == 1) {
             sl.v[0] = *reinterpret_cast<const KOHLER_GLOBAL uint32_t *>(rp + cv);
         } else if constexpr (NW == 2) {
@@ -285,7 +286,7 @@ __device__ __forceinline__ void load_slot(const Pix *row, int c, int W, RowSlot<
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < K; ++k) sl.v[k] = (uint32_t)rp[(uint32_t)(FULL ? c + k : min(c + k, W - 1))];
+        for (int k = 0; k < K; ++k) sl.v[k] = (uint32_t)rp[(uint32_t)element_column(c, k, W, FULL)];
     }
 }
 
@@ -594,7 +595,7 @@ __device__ __forceinline__ void pk_load(const KImage &im, int s, int64_t rb, int
     b.rb = rb;
     b.s = s;
     b.nr = (int)(r1 - rb);
-    b.erv = (uint32_t)gptr(base + (rb + min(lane, room)) * pitch)[(uint32_t)min<int64_t>((int64_t)(s + 1) * SW, im.W - 1)];
+    b.erv = (uint32_t)gptr(base + (rb + min(lane, room)) * pitch)[(uint32_t)right_edge_column(s, SW, im.W)];
     const uint8_t *rowp = base + rb * pitch;
 #pragma unroll
     for (int j = 0; j <= kPkRows; ++j) {
@@ -683,8 +684,8 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
 
     // the strip's edge columns, clamped into the image (a clamped value is never used: the pairs it
     // would form lie outside the image and are masked)
-    const uint32_t cr = (uint32_t)min<int64_t>((int64_t)(s + 1) * SW, W - 1);
-    const uint32_t cl = (uint32_t)max(s * SW - 1, 0);
+    const uint32_t cr = (uint32_t)right_edge_column(s, SW, W);
+    const uint32_t cl = (uint32_t)left_edge_column(s, SW);
     static_assert(B + 1 <= 64, "one lane per row of a batch holds its edge pixels");
 
     // last row a batch may touch: the halo row below the range, or the image's last row
@@ -762,22 +763,15 @@ __device__ __forceinline__ void strip_rows(const KImage &im, int s, int64_t r0, 
 template <typename Pix, int NB, int K, bool CLAMP, class Acc, class Spill>
 __device__ __forceinline__ void strip_range(const KImage &im, int s, int64_t r0, int64_t r1, uint32_t Mm1,
                                             Acc &acc, Spill &spill, uint32_t &vmax) {
-    constexpr int SW = 64 * K;
-    if constexpr (pk_form<Pix, NB, K, CLAMP, Acc>()) {
-        if (im.vec_ok && (int64_t)(s + 1) * SW <= im.W) {
-            pk_rows(im, s, r0, r1, acc, spill);
-            return;
-        }
-    }
-    if ((int64_t)(s + 1) * SW < im.W) {
-        if (im.vec_ok)
-            strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
-        else
-            strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
-    } else if (im.vec_ok && im.W % K == 0) {
-        strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax);
-    } else {
-        strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax);
+    constexpr bool kPk = pk_form<Pix, NB, K, CLAMP, Acc>();
+    switch (strip_path(s, K, im.W, im.vec_ok != 0, kPk)) {
+        case PATH_PK:
+            if constexpr (kPk) pk_rows(im, s, r0, r1, acc, spill);
+            break;
+        case PATH_FULL_PACKED: strip_rows<Pix, NB, K, CLAMP, true, true>(im, s, r0, r1, Mm1, acc, spill, vmax); break;
+        case PATH_FULL_ELEM: strip_rows<Pix, NB, K, CLAMP, true, false>(im, s, r0, r1, Mm1, acc, spill, vmax); break;
+        case PATH_LAST_PACKED: strip_rows<Pix, NB, K, CLAMP, false, true>(im, s, r0, r1, Mm1, acc, spill, vmax); break;
+        default: strip_rows<Pix, NB, K, CLAMP, false, false>(im, s, r0, r1, Mm1, acc, spill, vmax); break;
     }
 }
 
