@@ -59,7 +59,7 @@ bool valid_plan(const kohler_plan &pl, int dtype, int32_t M) {
 kohler_plan default_plan(int dtype, int32_t M) {
     kohler_plan pl{};
     pl.form = (M <= kMaxMBand) ? FORM_BAND : FORM_MARG;
-    pl.band = std::min(32, std::max(1, M - 1));
+    pl.band = std::min(31, std::max(1, M - 1));  // band + 1 a power of two: exact large-gap test
     pl.block = 512;
     pl.grid = 0;
     pl.px_per_lane = 4;
@@ -654,7 +654,7 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
     // candidate values of each knob
     std::vector<std::pair<int, int>> shapes;  // (form, band)
     if (M <= kMaxMBand)
-        for (int b : {8, 16, 24, 32, 48, 64})
+        for (int b : {7, 15, 23, 31, 47, 63})  // band + 1 = 2^k keeps the row's large-gap test exact
             if (b <= std::max(1, M - 1)) shapes.emplace_back(FORM_BAND, b);
     if (M <= kMaxMBand) shapes.emplace_back(FORM_TRI, 1);
     if (M <= kMaxMMarg) shapes.emplace_back(FORM_MARG, 1);
@@ -730,7 +730,7 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
         const kohler_plan base = cur;
         std::vector<int> bands = {base.band};
         if (base.form == FORM_BAND)
-            for (int b : {16, 32, 48, 64})
+            for (int b : {15, 31, 47, 63})
                 if (b != base.band && b <= std::max(1, M - 1)) bands.push_back(b);
         for (int bv : bands)
             for (int pv : ppls) {

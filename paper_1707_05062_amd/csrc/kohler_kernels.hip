@@ -335,7 +335,7 @@ struct BandAcc {
     u16x2 coff;     // [c, c]
     u16x2 nfix;     // [0, c - c'] (mod 2^16): re-bases a value taken from the next lane (copy c')
     u16x2 cap2;     // [C (nb + 1), C (nb + 1)]
-    u16x2 dmax2;    // largest C d seen since the last test, per half
+    u16x2 dmax2;    // bitwise OR of the C d seen since the last test, per half (see needs_spill2)
     static constexpr uint32_t kScale = 4;
     __device__ __forceinline__ void pair(uint32_t x4, uint32_t y4, bool valid) {
         if (!valid) {
@@ -356,14 +356,16 @@ struct BandAcc {
     __device__ __forceinline__ void pairs2(u16x2 x, u16x2 y) {
         const u16x2 lo = __builtin_elementwise_min(x, y);
         const u16x2 d = __builtin_elementwise_max(x, y) - lo;
-        dmax2 = __builtin_elementwise_max(dmax2, d);
+        dmax2 = as_u16x2(as_u32(dmax2) | as_u32(d));
         const u16x2 w = __builtin_elementwise_min(d, cap2) * (uint16_t)kRowStride + lo;
         // each half times 4 is one shift with a 16-bit source selection (SDWA)
         lds_inc(lds_at((uint32_t)w.x * 4u));
         lds_inc(lds_at((uint32_t)w.y * 4u));
     }
     __device__ __forceinline__ bool needs_spill2() const {
-        return max((uint32_t)dmax2.x, (uint32_t)dmax2.y) >= (uint32_t)cap2.x;
+        // the OR of the gaps is at least their maximum, so no large gap is missed; when cap2 is a
+        // power of two (band + 1 = 2^k / C) the test is exact, else a row may be re-run needlessly
+        return ((uint32_t)dmax2.x | (uint32_t)dmax2.y) >= (uint32_t)cap2.x;
     }
     __device__ __forceinline__ void pixel(uint32_t, uint32_t, bool) {}
     static constexpr bool kPixels = false;
@@ -559,14 +561,23 @@ constexpr int slot_batch() {
 
 // ------------------------------------------------------------------------------------------------
 // Full, aligned strips of 8-bit pixels (8 per lane, 4-neighbourhood, banded form, no clamping):
-// batches of kPkRows rows, software-pipelined (the loads of the next batch are in flight while this
-// one is used), with the pairs formed two per instruction (band_row_pairs).
+// batches of kPkRows rows (longer ranges keep the next batch's loads in flight while one is used),
+// with the pairs formed two per instruction (band_row_pairs). The single-image launch deals chunks
+// of one batch: 4 rows balanced the waves best on the 18 MP image (3, 5, 6, 9 and 12 were slower:
+// larger chunks leave the waves of a workgroup further apart, 3 rows cost more in halo loads).
 
 #ifndef KOHLER_PK_ROWS
-#define KOHLER_PK_ROWS 6
+#define KOHLER_PK_ROWS 4
 #endif
 constexpr int kPkRows = KOHLER_PK_ROWS;
-static_assert(kPkRows >= 1 && kPkRows < 64, "one lane per row of a batch holds its edge pixel");
+
+// The single-image launch splits each workgroup's last blockDim >> kTailShift chunks in halves.
+#ifndef KOHLER_TAIL_SHIFT
+#define KOHLER_TAIL_SHIFT 7
+#endif
+constexpr int kTailShift = KOHLER_TAIL_SHIFT;
+static_assert(kPkRows >= 3 && kPkRows < 64,
+              "chunks of at least 3 rows of 512 columns (chunk numbers stay 32-bit); one lane per row holds its edge pixel");
 
 // Whether an instance takes this path (for the strips that lie wholly inside the image).
 template <typename Pix, int NB, int K, bool CLAMP, class Acc>
@@ -1588,9 +1599,13 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
 
     // rows a wave processes at a time: a chunk of the single-image launch, a claim of the batched one
     constexpr int B = row_batch<Pix, NB, K, CLAMP>();
+    // the single-image launch of the 8-bit packed instances deals chunks of one packed batch
+    constexpr bool kPkKernel =
+        FORM == FORM_BAND && std::is_same<Pix, uint8_t>::value && K == 8 && NB == 4 && !CLAMP;
+    constexpr int BD = kPkKernel ? kPkRows : B;
 
     if (p.dyn) {
-        // One image: a chunk is B consecutive rows of one strip. Chunks are numbered row-block major
+        // One image: a chunk is BD consecutive rows of one strip. Chunks are numbered row-block major
         // (chunk c covers strip c mod nstrips of row block c / nstrips), so neighbouring strips of
         // the same rows get consecutive numbers, and they are dealt round-robin to the workgroups
         // (chunk c to logical workgroup c mod G): every workgroup samples the whole image, costly
@@ -1600,7 +1615,7 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
         // pieces so that the waves finish closer together.
         const KImage im = image_desc(p, 0);
         const int64_t ns = im.nstrips;
-        const int64_t nblocks = (im.H + B - 1) / B;
+        const int64_t nblocks = (im.H + BD - 1) / BD;
         const int64_t nchunks = nblocks * ns;
         // number of chunks c < n with c = g (mod G)
         auto upto = [&](int64_t n) -> int64_t { return n > g ? (n - g - 1) / G + 1 : 0; };
@@ -1613,25 +1628,26 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
             return (uint32_t)__builtin_amdgcn_readfirstlane(k);
         };
         const uint32_t vmax = accumulate([&](auto &acc, auto &spill, uint32_t &vm, uint32_t mm1) {
-            // chunk numbers stay below 2^32 (at most 2^40 pixels, chunks of B >= 4 rows by at least
-            // 256 columns), so the decode is a 32-bit division by a wave-uniform value
-            constexpr uint32_t kHalf = (uint32_t)B / 2, kPieces = 2;
-            const uint32_t ntail = (uint32_t)min<int64_t>(mine, (int64_t)(blockDim.x >> 7));
+            // chunk numbers stay below 2^32 (at most 2^40 pixels, chunks of at least 1024: B >= 4 rows
+            // by 256 columns, or kPkRows >= 3 rows by 512), so the decode is a 32-bit division by a
+            // wave-uniform value
+            constexpr uint32_t kHalf = (uint32_t)BD / 2, kPieces = 2;
+            const uint32_t ntail = (uint32_t)min<int64_t>(mine, (int64_t)(blockDim.x >> kTailShift));
             const uint32_t whole = (uint32_t)mine - ntail;
             const uint32_t nclaims = whole + ntail * kPieces;
             // strip and rows [r0, r1) of claim j (empty: a piece past the last row of a short final
             // row block)
             auto decode = [&](uint32_t j, int &strip, int64_t &r0, int64_t &r1) {
-                uint32_t jc = j, off = 0, len = (uint32_t)B;
+                uint32_t jc = j, off = 0, len = (uint32_t)BD;
                 if (j >= whole) {
                     jc = whole + (j - whole) / kPieces;
                     off = ((j - whole) % kPieces) * kHalf;
-                    len = off ? (uint32_t)B - kHalf : kHalf;
+                    len = off ? (uint32_t)BD - kHalf : kHalf;
                 }
                 const uint32_t c = (uint32_t)g + jc * (uint32_t)G;
                 const uint32_t blk = c / (uint32_t)ns;
                 strip = (int)(c - blk * (uint32_t)ns);
-                r0 = (int64_t)blk * B + off;
+                r0 = (int64_t)blk * BD + off;
                 r1 = min(im.H, r0 + (int64_t)len);
             };
             for (uint32_t j = claim(); j < nclaims; j = claim()) {
@@ -1641,9 +1657,9 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
                 if (r0 < r1) strip_range<Pix, NB, K, CLAMP>(im, strip, r0, r1, mm1, acc, spill, vm);
             }
         });
-        // units of this workgroup: B rows per chunk, less the short chunks of the last row block
-        const int64_t last_rows = im.H - (nblocks - 1) * B;
-        const int64_t units = mine * B - (upto(nchunks) - upto(nchunks - ns)) * (B - last_rows);
+        // units of this workgroup: BD rows per chunk, less the short chunks of the last row block
+        const int64_t last_rows = im.H - (nblocks - 1) * BD;
+        const int64_t units = mine * BD - (upto(nchunks) - upto(nchunks - ns)) * (BD - last_rows);
         flush(im, vmax, units, im.nunits);
         return;
     }

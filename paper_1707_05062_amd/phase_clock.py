@@ -67,7 +67,7 @@ def breakdown(slots: np.ndarray, waves: np.ndarray, grid: int, nwaves: int) -> d
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--plan", default="1:32:512:512:8:4", help="form:band:block:grid:px_per_lane:replicas[:copies]")
+    ap.add_argument("--plan", default="1:31:1024:256:8:8:4", help="form:band:block:grid:px_per_lane:replicas[:copies]")
     ap.add_argument("--launches", type=int, default=30)
     ap.add_argument("--rotate", type=int, default=32)
     ap.add_argument("--lib", default="", help="another measurement build of the library (default: libkohler_phase.so)")
