@@ -149,11 +149,14 @@ struct NbParams {
     int32_t tile_rows;            // image rows per tile
     uint32_t tile_off;            // LDS byte offset of the value tile
     uint32_t bs_off;              // LDS byte offset of the workgroup scratch
+    uint32_t raw_off;             // LDS byte offset of the unfiltered tile (pre-filter only)
+    uint32_t offs_off;            // LDS byte offset of the copy of fdy, fdx (8 kNbMaxHalf bytes)
     int32_t pad;
     int64_t tiles_x, tiles;       // tiles per band of tile_rows rows, and in all
 };
 
-// LDS layout of an nbhd_kernel launch: fills tile_rows, tile_off and bs_off and returns the bytes.
+// LDS layout of an nbhd_kernel launch: fills tile_rows, tile_off, raw_off, offs_off and bs_off and returns the
+// bytes (radius, filter and k.M set).
 size_t nbhd_lds_layout(NbParams &q, int form, int block);
 // Workgroups of an nbhd_kernel instance that fit on one compute unit.
 int nbhd_blocks_per_cu(int dtype, int form, int M, int block, size_t lds);

@@ -1726,6 +1726,83 @@ __device__ __forceinline__ uint32_t binomial3_at(const KImage &im, int64_t y, in
     return (rows[0] + 2u * rows[1] + rows[2] + 8u) >> 4;
 }
 
+// Staging of a tile: rows y0 .. y0 + nrows - 1 and columns x0 .. x0 + ncols - 1 of the image (y0 >= -1,
+// y0 < H, ncols at most twice the block) are loaded into registers, two column slots per thread and
+// every row of a slot in flight together, while the previous tile's pairs are formed; then stored
+// to LDS. Every address is clamped into the image. MODE: STAGE_MARK stores kNbOut for positions
+// outside the image and clamps values to M - 1 (when CLAMP); STAGE_RAW stores the clamped position's
+// pixel unchanged (the pre-filter's border). With CLAMP, vmax takes the tile's own pixels: rows
+// own_r .. own_r + own_rows - 1 and columns own_c .. own_c + blockDim - 1, inside the image.
+constexpr int kNbMaxStage = 16 + kNbMaxRadius + 2;  // rows of a staged region (tile rows <= 16)
+enum StageMode { STAGE_MARK, STAGE_RAW };
+// Tile value of a position outside the image (above any level: values are at most M - 1 <= 8191).
+constexpr uint32_t kNbOut = 0xFFFFu;
+
+struct StageRegs {
+    uint32_t v[2][kNbMaxStage];
+};
+
+struct StageRegion {
+    int64_t y0;
+    int x0, nrows, ncols;
+    int own_r, own_rows, own_c;
+};
+
+template <typename Pix>
+__device__ __forceinline__ void load_region(const KImage &im, const StageRegion &g, StageRegs &sr) {
+    const int64_t H = im.H;
+    const int W = (int)im.W;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int rx = (int)threadIdx.x + j * (int)blockDim.x;
+        if (rx < g.ncols) {
+            const int x = g.x0 + rx;
+            const int xc = x < 0 ? 0 : (x >= W ? W - 1 : x);
+#pragma unroll
+            for (int r = 0; r < kNbMaxStage; ++r) {
+                if (r < g.nrows) {  // uniform; nothing but the load, so that no wait is needed here
+                    const int64_t y = g.y0 + r;
+                    sr.v[j][r] = image_px<Pix>(im, y < 0 ? 0 : (y >= H ? H - 1 : y), xc);
+                }
+            }
+        }
+    }
+}
+
+template <int MODE, bool CLAMP>
+__device__ __forceinline__ void store_region(const KImage &im, const StageRegion &g, const StageRegs &sr,
+                                             KOHLER_LDS uint16_t *dst, uint32_t mm1, uint32_t &vmax) {
+    const int W = (int)im.W;
+    const int TW = (int)blockDim.x;
+    // rows of the region inside the image: [in0, in1)
+    const int in0 = g.y0 < 0 ? 1 : 0;
+    const int64_t hy = im.H - g.y0;
+    const int in1 = hy < g.nrows ? (int)hy : g.nrows;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int rx = (int)threadIdx.x + j * TW;
+        if (rx < g.ncols) {
+            const int x = g.x0 + rx;
+            const bool xin = x >= 0 && x < W;
+            const bool own_x = xin && rx >= g.own_c && rx < g.own_c + TW;
+#pragma unroll
+            for (int r = 0; r < kNbMaxStage; ++r) {
+                if (r < g.nrows) {
+                    uint32_t v = sr.v[j][r];
+                    if constexpr (CLAMP) {
+                        if (own_x && r >= g.own_r && r < g.own_r + g.own_rows) vmax = max(vmax, v);
+                    }
+                    if constexpr (MODE == STAGE_MARK) {
+                        if constexpr (CLAMP) v = min(v, mm1);
+                        v = (xin && r >= in0 && r < in1) ? v : kNbOut;
+                    }
+                    dst[r * g.ncols + rx] = (uint16_t)v;
+                }
+            }
+        }
+    }
+}
+
 template <typename Pix, int FORM, bool CLAMP>
 __global__ void __launch_bounds__(kNbBlock) nbhd_kernel(NbParams q) {
     extern __shared__ __align__(16) uint32_t lds_raw[];
@@ -1754,51 +1831,153 @@ __global__ void __launch_bounds__(kNbBlock) nbhd_kernel(NbParams q) {
     }();
     uint32_t vmax = 0;
     int64_t mine = 0;
+    const int W32 = (int)W;  // W <= 2^30: columns are 32-bit; rows are counted from the tile's first
+    KOHLER_LDS uint16_t *raw = reinterpret_cast<KOHLER_LDS uint16_t *>(reinterpret_cast<KOHLER_LDS uint8_t *>(lds) +
+                                                                       q.raw_off);
+    const int F = q.filter ? 1 : 0;
+    // the half offsets as tile offsets dy TC + dx, one per lane (lane 16 par + a), read once and then
+    // taken with a lane read by the wave-uniform index: indexing the argument with a loop variable
+    // would read it from memory on every use
+    const int lane = (int)(threadIdx.x & 63u);
+    const int lpar = (lane >> 4) & 1, la = lane & 15;
+    const int offv = (int)q.hdy[lpar][la] * TC + (int)q.hdx[lpar][la];
+    const int na0 = q.nhalf[0], na1 = q.nhalf[1], na_max = max(na0, na1);
+    [[maybe_unused]] const int nf0 = q.nfull[0], nf1 = q.nfull[1];
+    // whole-neighbourhood offsets (degrees of the pixels near the border): a copy in LDS, per parity
+    // 2 kNbMaxHalf dy then 2 kNbMaxHalf dx (visible to all after the first tile's barrier)
+    [[maybe_unused]] KOHLER_LDS int8_t *foffs =
+        reinterpret_cast<KOHLER_LDS int8_t *>(reinterpret_cast<KOHLER_LDS uint8_t *>(lds) + q.offs_off);
+    if constexpr (FORM == FORM_MARG) {
+        if (threadIdx.x < 8 * kNbMaxHalf) {
+            const int par = (int)threadIdx.x / (4 * kNbMaxHalf), i = (int)threadIdx.x % (4 * kNbMaxHalf);
+            foffs[threadIdx.x] = i < 2 * kNbMaxHalf ? q.fdy[par][i] : q.fdx[par][i - 2 * kNbMaxHalf];
+        }
+    }
+    // tile t: first row r0, first column c0
+    auto tile_at = [&](int64_t t, int64_t &r0, int &c0) {
+        const int64_t ty = t / q.tiles_x;
+        r0 = ty * TH;
+        c0 = (int)(t - ty * q.tiles_x) * TW;
+    };
+    // 1. the tile's values. Unfiltered: rows r0 .. r0 + TH + R - 1 and columns c0 - R .. c0 + TW + R - 1
+    //    into the tile (kNbOut outside the image). Filtered: one more row and column on every side
+    //    into the raw tile, with coordinates clamped into the image (the filter's border rule), then
+    //    the filter from LDS into the tile. Each image pixel is range-checked by the tile that owns it.
+    const int st_rows = TH + R + 2 * F, st_cols = TC + 2 * F;
+    StageRegs sr;
+    // the staged region of tile t (its row stride in LDS is its width)
+    auto region_of = [&](int64_t t) {
+        int64_t r0;
+        int c0;
+        tile_at(t, r0, c0);
+        const int own = (int)min<int64_t>(TH, H - r0);
+        return F ? StageRegion{r0 - 1, c0 - R - 1, st_rows, st_cols, 1, own, R + 1}
+                 : StageRegion{r0, c0 - R, st_rows, st_cols, 0, own, R};
+    };
+    auto load_tile = [&](int64_t t) { load_region<Pix>(im, region_of(t), sr); };
+    if (g < q.tiles) load_tile(g);
     for (int64_t t = g; t < q.tiles; t += G, ++mine) {
-        const int64_t ty = t / q.tiles_x, tx = t - ty * q.tiles_x;
-        const int64_t r0 = ty * TH, c0 = tx * TW;
-        // 1. the tile's values; each image pixel is range-checked by the tile that owns it
-        for (int i = (int)threadIdx.x; i < (TH + R) * TC; i += TW) {
-            const int ry = i / TC, rx = i - ry * TC;
-            const int64_t y = r0 + ry, x = c0 - R + rx;
-            uint32_t v = 0;
-            if (y < H && x >= 0 && x < W) {
-                uint32_t raw;
-                if (q.filter) v = binomial3_at<Pix>(im, y, x, raw);
-                else v = raw = image_px<Pix>(im, y, x);
-                if constexpr (CLAMP) {
-                    if (ry < TH && rx >= R && rx < R + TW) vmax = max(vmax, raw);
-                    v = min(v, Mm1);
-                }
-            }
-            tile[i] = (uint16_t)v;
-        }
+        int64_t r0;
+        int c0;
+        tile_at(t, r0, c0);
+        const int rows_left = (int)min<int64_t>(H - r0, (int64_t)1 << 30);  // image rows from r0 on
+        const int above = r0 > kNbMaxRadius ? kNbMaxRadius : (int)r0;        // image rows above r0 in reach
+        const int own = min(TH, rows_left);
+        // every pixel of the tile has its whole neighbourhood inside the image (all R rows and columns
+        // around the tile are image pixels): no pair or degree needs a test
+        const bool interior = r0 >= R && TH + R <= rows_left && c0 >= R && c0 + TW + R <= W32;
+        if (F) store_region<STAGE_RAW, CLAMP>(im, region_of(t), sr, raw, Mm1, vmax);
+        else store_region<STAGE_MARK, CLAMP>(im, region_of(t), sr, tile, Mm1, vmax);
         __syncthreads();
-        // 2. the pairs of the tile's own pixels, one column per thread
-        const int64_t x = c0 + threadIdx.x;
-        const bool inx = x < W;
-        for (int ry = 0; ry < TH; ++ry) {
-            const int64_t y = r0 + ry;
-            if (y >= H) break;  // uniform
-            const int par = (int)(y & 1);
-            const uint32_t v = tile[ry * TC + R + (int)threadIdx.x];
-            const typename Acc::P pv = Acc::prep(v);
-            for (int a = 0; a < q.nhalf[par]; ++a) {
-                const int dy = q.hdy[par][a], dx = q.hdx[par][a];
-                const int64_t y1 = y + dy, x1 = x + dx;
-                const bool valid = inx && y1 < H && x1 >= 0 && x1 < W;
-                const uint32_t w = tile[(ry + dy) * TC + R + (int)threadIdx.x + dx];
-                acc.pair(pv, Acc::prep(w), valid);
-            }
-            if constexpr (FORM == FORM_MARG) {
-                uint32_t deg = 0;
-                for (int b = 0; b < q.nfull[par]; ++b) {
-                    const int64_t y1 = y + q.fdy[par][b], x1 = x + q.fdx[par][b];
-                    deg += (y1 >= 0 && y1 < H && x1 >= 0 && x1 < W) ? 1u : 0u;
+        if (F) {
+            for (int rx = (int)threadIdx.x; rx < TC; rx += TW) {
+                const int xf = c0 - R + rx;
+                const bool xout = xf < 0 || xf >= W32;
+                const KOHLER_LDS uint16_t *s = raw + rx;
+                auto hsum = [&](int i) {
+                    return (uint32_t)s[i * (TC + 2)] + 2u * (uint32_t)s[i * (TC + 2) + 1] + (uint32_t)s[i * (TC + 2) + 2];
+                };
+                uint32_t h0 = hsum(0), h1 = hsum(1);
+                for (int ry = 0; ry < TH + R; ++ry) {
+                    const uint32_t h2 = hsum(ry + 2);
+                    uint32_t v = (h0 + 2u * h1 + h2 + 8u) >> 4;
+                    if constexpr (CLAMP) v = min(v, Mm1);
+                    tile[ry * TC + rx] = (uint16_t)((xout || ry >= rows_left) ? kNbOut : v);
+                    h0 = h1;
+                    h1 = h2;
                 }
-                acc.pixel(v, deg, inx);
             }
+            __syncthreads();
         }
+        // the next tile's loads are in flight while this tile's pairs are formed
+        if (t + G < q.tiles) load_tile(t + G);
+        // 2. the pairs of the tile's own pixels, one column per thread, rows in groups of four (their
+        //    LDS reads in flight together); a row of parity par takes that parity's half offsets. An
+        //    interior tile takes every pair and the whole degree without a test.
+        const int x = c0 + (int)threadIdx.x;
+        const int par0 = (int)(r0 & 1);
+        const KOHLER_LDS uint16_t *col = tile + R + (int)threadIdx.x;
+        auto pass = [&](auto in_tag) {
+            constexpr bool IN = decltype(in_tag)::value;
+            for (int ry = 0; ry < own; ry += 4) {
+                uint32_t v[4];
+                typename Acc::P pv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    v[k] = col[min(ry + k, own - 1) * TC];
+                    pv[k] = Acc::prep(v[k]);
+                }
+                for (int a = 0; a < na_max; ++a) {
+                    uint32_t w[4];
+                    bool ok[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int pk = (par0 + k) & 1;  // ry is a multiple of 4
+                        const int o = __builtin_amdgcn_readlane(offv, 16 * pk + a);
+                        const int r = min(ry + k, own - 1);
+                        // the row and the offset exist (uniform); then, off the interior, both pixels
+                        // lie inside the image
+                        ok[k] = ry + k < own && a < (pk ? na1 : na0);
+                        // offsets past a parity's count are zero: the read stays on the tile
+                        w[k] = col[r * TC + o];
+                        if constexpr (!IN) ok[k] = ok[k] && max(v[k], w[k]) != kNbOut;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        if constexpr (IN) {
+                            if (ok[k]) acc.pair(pv[k], Acc::prep(w[k]), true);
+                        } else {
+                            acc.pair(pv[k], Acc::prep(w[k]), ok[k]);
+                        }
+                    }
+                }
+                if constexpr (FORM == FORM_MARG) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int pk = (par0 + k) & 1;
+                        const int nf = pk ? nf1 : nf0;
+                        const int ryk = ry + k;
+                        if constexpr (IN) {
+                            if (ryk < own) acc.pixel(v[k], (uint32_t)nf, true);
+                        } else {
+                            // a pixel at least R rows and columns inside the image has the whole neighbourhood
+                            uint32_t deg = (uint32_t)nf;
+                            if (!(ryk >= R - above && ryk < rows_left - R && x >= R && x < W32 - R)) {
+                                deg = 0;
+                                const KOHLER_LDS int8_t *fo = foffs + pk * 4 * kNbMaxHalf;
+                                for (int b = 0; b < nf; ++b) {
+                                    const int ry1 = ryk + fo[b], x1 = x + fo[2 * kNbMaxHalf + b];
+                                    deg += (ry1 >= -above && ry1 < rows_left && (uint32_t)x1 < (uint32_t)W32) ? 1u : 0u;
+                                }
+                            }
+                            acc.pixel(v[k], deg, ryk < own && v[k] != kNbOut);
+                        }
+                    }
+                }
+            }
+        };
+        if (interior) pass(std::true_type{});
+        else pass(std::false_type{});
         __syncthreads();  // before the next tile is staged over this one
     }
     flush_image<FORM, CLAMP>(p, lds, bs, im, vmax, mine, q.tiles);
@@ -1883,18 +2062,30 @@ int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int ban
 }
 
 size_t nbhd_lds_layout(NbParams &q, int form, int block) {
-    // the tables (or the finishing step's arrays) first, then the value tile, then the scratch; as
-    // many tile rows as fit (at most 16)
+    // the tables (or the finishing step's arrays) first, then the value tile, then (pre-filter only)
+    // the raw tile with one more row and column on every side, then the whole-neighbourhood offsets,
+    // then the scratch. Tile rows: the most that fit, at most 16.
     const size_t table = lds_main_bytes(form, q.k.M, 1, block, 1);
     const size_t tile_off = (table + 15) & ~(size_t)15;
-    const size_t row_bytes = (size_t)(block + 2 * q.radius) * sizeof(uint16_t);
+    const int R = q.radius, F = q.filter ? 1 : 0;
     const size_t room = kMaxLdsBytes - sizeof(BlockScratch) - 16;
-    int rows = 16;
-    while (rows > 1 && tile_off + (size_t)(rows + q.radius) * row_bytes > room) --rows;
-    q.tile_rows = rows;
+    auto bytes_for = [&](int rows, size_t &raw_off, size_t &bs_off) {
+        const size_t tile = (size_t)(rows + R) * (size_t)(block + 2 * R) * sizeof(uint16_t);
+        raw_off = (tile_off + tile + 15) & ~(size_t)15;
+        const size_t rawb = F ? (size_t)(rows + R + 2) * (size_t)(block + 2 * R + 2) * sizeof(uint16_t) : 0;
+        q.offs_off = (uint32_t)((raw_off + rawb + 15) & ~(size_t)15);
+        bs_off = (q.offs_off + 8 * kNbMaxHalf + 15) & ~(size_t)15;
+        return bs_off;
+    };
+    int best = 16;
+    size_t raw_off = 0, bs_off = 0;
+    while (best > 1 && bytes_for(best, raw_off, bs_off) > room) --best;
+    bytes_for(best, raw_off, bs_off);
+    q.tile_rows = best;
     q.tile_off = (uint32_t)tile_off;
-    q.bs_off = (uint32_t)((tile_off + (size_t)(rows + q.radius) * row_bytes + 15) & ~(size_t)15);
-    return (size_t)q.bs_off + sizeof(BlockScratch);
+    q.raw_off = (uint32_t)raw_off;
+    q.bs_off = (uint32_t)bs_off;
+    return bs_off + sizeof(BlockScratch);
 }
 
 int nbhd_blocks_per_cu(int dtype, int form, int M, int block, size_t lds) {
