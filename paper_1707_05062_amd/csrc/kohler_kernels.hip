@@ -32,6 +32,7 @@
 // wave range). Horizontal neighbours across lanes come from DPP wave shifts; only lanes 0 and 63
 // load one extra pixel per row.
 
+#include <mutex>
 #include <type_traits>
 
 #include "kohler_impl.h"
@@ -2019,8 +2020,66 @@ const void *pick_kernel(int dtype, int nbhd, int form, int px_per_lane, int M) {
     return nbhd == 4 ? pick_form<uint16_t, 4, 4>(form, true) : pick_form<uint16_t, 8, 4>(form, true);
 }
 
+// hipFuncSetAttribute and the occupancy query cost host time on every call, so their results are
+// kept per device and kernel (the occupancy per block size and LDS bytes too) in fixed tables: no
+// heap allocation, and when a table is full the call is simply made again.
+constexpr int kKernCache = 256;
+struct KernCache {
+    std::mutex mu;
+    int n_attr = 0, n_occ = 0;
+    struct Attr {
+        int dev;
+        const void *kern;
+    } attr[kKernCache];
+    struct Occ {
+        int dev;
+        const void *kern;
+        int block;
+        size_t lds;
+        int n;
+    } occ[kKernCache];
+};
+KernCache &kern_cache() {
+    static KernCache c;
+    return c;
+}
+
 hipError_t allow_large_lds(const void *kern) {
-    return hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    KernCache &c = kern_cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (int i = 0; i < c.n_attr; ++i)
+            if (c.attr[i].dev == dev && c.attr[i].kern == kern) return hipSuccess;
+    }
+    e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(c.mu);
+        if (c.n_attr < kKernCache) c.attr[c.n_attr++] = {dev, kern};
+    }
+    return e;
+}
+
+// Workgroups of `kern` with `block` threads and `lds` bytes that fit on one compute unit (>= 1).
+int occupancy(const void *kern, int block, size_t lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1;
+    KernCache &c = kern_cache();
+    {
+        std::lock_guard<std::mutex> lk(c.mu);
+        for (int i = 0; i < c.n_occ; ++i)
+            if (c.occ[i].dev == dev && c.occ[i].kern == kern && c.occ[i].block == block && c.occ[i].lds == lds)
+                return c.occ[i].n;
+    }
+    if (allow_large_lds(kern) != hipSuccess) return 1;
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds) != hipSuccess) return 1;
+    n = n > 0 ? n : 1;
+    std::lock_guard<std::mutex> lk(c.mu);
+    if (c.n_occ < kKernCache) c.occ[c.n_occ++] = {dev, kern, block, lds, n};
+    return n;
 }
 
 }  // namespace
@@ -2052,13 +2111,7 @@ int max_block_for(int dtype, int nbhd, int form, int px_per_lane, int M) {
 }
 
 int blocks_per_cu(int dtype, int nbhd, int form, int px_per_lane, int M, int band, int block, int copies) {
-    const void *kern = pick_kernel(dtype, nbhd, form, px_per_lane, M);
-    if (allow_large_lds(kern) != hipSuccess) return 1;
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds_bytes(form, M, band, block, copies)) !=
-        hipSuccess)
-        return 1;
-    return n > 0 ? n : 1;
+    return occupancy(pick_kernel(dtype, nbhd, form, px_per_lane, M), block, lds_bytes(form, M, band, block, copies));
 }
 
 size_t nbhd_lds_layout(NbParams &q, int form, int block) {
@@ -2089,11 +2142,7 @@ size_t nbhd_lds_layout(NbParams &q, int form, int block) {
 }
 
 int nbhd_blocks_per_cu(int dtype, int form, int M, int block, size_t lds) {
-    const void *kern = pick_nbhd_kernel(dtype, form, M);
-    if (allow_large_lds(kern) != hipSuccess) return 1;
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, block, lds) != hipSuccess) return 1;
-    return n > 0 ? n : 1;
+    return occupancy(pick_nbhd_kernel(dtype, form, M), block, lds);
 }
 
 hipError_t launch_nbhd(const NbParams &q, int dtype, int form, int block, int grid, size_t lds,
