@@ -180,9 +180,10 @@ int kohler_curve_nbhd_async(kohler_ctx *ctx, const void *d_img, int dtype, int64
  *   replicas    merge schedule: copies of the per-image device accumulators that the workgroups'
  *               partial histograms are added into (1..16; 0 = automatic, about one per 32
  *               workgroups); the finishing workgroup sums the copies
- *   copies      LDS privatisation width of the banded form: copies of the joint table each
- *               workgroup keeps, lane l of a wave adding to copy l % copies (1, 2 or 4; 0 =
- *               automatic; other forms use 1)
+ *   copies      LDS privatisation width: copies of the tables each workgroup keeps, interleaved
+ *               word by word, lane l of a wave adding to copy l % copies (banded form 1, 2 or 4;
+ *               marginal form 1 or 2, as the LDS allows: 4 M words per copy; triangular form 1;
+ *               0 = automatic: 2 for the banded form, else 1)
  *   acc_split   layout of the device accumulators: 0 = automatic (one int64 word per grey level
  *               holding E * 2^32 + D1 while the image, or every image of a batched launch, has
  *               fewer than 2^30 neighbour pairs, else two words), 1 = always two words (D1 and E

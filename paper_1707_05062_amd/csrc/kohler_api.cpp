@@ -47,7 +47,8 @@ bool valid_plan(const kohler_plan &pl, int dtype, int32_t M) {
     if (pl.form == FORM_MARG && M > kMaxMMarg) return false;
     if (pl.block != 256 && pl.block != 512 && pl.block != 1024) return false;
     if (pl.copies != 1 && pl.copies != 2 && pl.copies != 4) return false;
-    if (pl.form != FORM_BAND && pl.copies != 1) return false;
+    if (pl.form == FORM_TRI && pl.copies != 1) return false;
+    if (pl.form == FORM_MARG && pl.copies > 2) return false;
     if (pl.acc_split != 0 && pl.acc_split != 1) return false;
     if (pl.grid < 0 || pl.grid > 65535) return false;
     if (pl.replicas < 0 || pl.replicas > kMaxReplicas) return false;
@@ -689,9 +690,10 @@ int kohler_autotune(kohler_ctx *ctx, int32_t n, const void *const *d_imgs, const
             else if (base_shape.form != FORM_BAND) pl.copies = 2;
             try_plan(pl);
         }
-        if (cur.form == FORM_BAND) {
+        if (cur.form != FORM_TRI) {  // table copies: 1, 2 or 4 (banded), 1 or 2 (marginal, as LDS allows)
             const kohler_plan base_copies = cur;
             for (int v : {1, 2, 4}) {
+                if (cur.form == FORM_MARG && v > 2) continue;
                 kohler_plan pl = base_copies;
                 pl.copies = v;
                 try_plan(pl);

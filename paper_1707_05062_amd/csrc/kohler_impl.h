@@ -97,16 +97,21 @@ constexpr int kMaxBandCopies = 4;
 // LDS bytes before the BlockScratch: the histogram tables, or the finalize step's arrays, whichever
 // is larger; 16-byte aligned. Finalize for M <= 256 needs 8 KiB (the curve and per-wave masks); for
 // larger M, two int64 arrays of block + 1 entries and one byte per grey level.
+// Finishing step for M > 256: M flag bytes (within the first 16 (block + 1) + M bytes), then (from
+// this byte offset) the replica sums of the M levels, one uint64 each.
+__host__ __device__ inline size_t fin_gather_offset(int M, int block) {
+    return (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
+}
+
 __host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int block, int copies) {
     // banded form: `copies` tables of band + 2 rows, then the hmax and hsum tables of the gaps beyond
     // the band (768 words); triangular form: M (M + 1) / 2 counters, 64 invalid-pair words, then
     // hmin, hmax (M each) and hsum (2M, one spare)
     const size_t words = (form == FORM_BAND)  ? (size_t)copies * ((size_t)band + 2) * kRowStride + 768
                          : (form == FORM_TRI) ? (size_t)M * (M + 1) / 2 + 64 + 4 * (size_t)M
-                                              : 4 * (size_t)M;
+                                              : 4 * (size_t)M * (size_t)copies;
     const size_t table = (words * 4 + 15) & ~(size_t)15;
-    const size_t fin = M <= 256 ? (size_t)8192
-                                : (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
+    const size_t fin = M <= 256 ? (size_t)8192 : fin_gather_offset(M, block) + 8 * (size_t)M;
     return table > fin ? table : fin;
 }
 

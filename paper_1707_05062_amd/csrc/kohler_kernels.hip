@@ -170,69 +170,6 @@ __device__ __forceinline__ int cmp_curve(int64_t su, int64_t ku, int64_t sv, int
 
 typedef KOHLER_LDS BlockScratch LdsScratch;
 
-// Inclusive prefix sum over the workgroup (blockDim.x a multiple of 64, at most 1024 threads).
-__device__ int64_t block_scan(int64_t x, LdsScratch &bs, int64_t &total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t y = __shfl_up(x, off, 64);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) bs.scan[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int w = 0; w < nw; ++w) {
-            run += bs.scan[w];
-            bs.scan[w] = run;
-        }
-    }
-    __syncthreads();
-    if (wid > 0) x += bs.scan[wid - 1];
-    total = bs.scan[nw - 1];
-    __syncthreads();
-    return x;
-}
-
-// Three inclusive prefix sums over the workgroup in one round of barriers.
-__device__ void block_scan3(int64_t (&x)[3], LdsScratch &bs, int64_t (&total)[3]) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const int64_t y = __shfl_up(x[q], off, 64);
-            if (lane >= off) x[q] += y;
-        }
-    }
-    if (lane == 63) {
-        bs.scan[wid] = x[0];
-        bs.red_s[wid] = x[1];
-        bs.red_k[wid] = x[2];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t r0 = 0, r1 = 0, r2 = 0;
-        for (int w = 0; w < nw; ++w) {
-            r0 += bs.scan[w];
-            bs.scan[w] = r0;
-            r1 += bs.red_s[w];
-            bs.red_s[w] = r1;
-            r2 += bs.red_k[w];
-            bs.red_k[w] = r2;
-        }
-    }
-    __syncthreads();
-    if (wid > 0) {
-        x[0] += bs.scan[wid - 1];
-        x[1] += bs.red_s[wid - 1];
-        x[2] += bs.red_k[wid - 1];
-    }
-    total[0] = bs.scan[nw - 1];
-    total[1] = bs.red_s[nw - 1];
-    total[2] = bs.red_k[nw - 1];
-    __syncthreads();
-}
 
 __device__ __forceinline__ uint32_t wave_max(uint32_t v) {
 #pragma unroll
@@ -485,20 +422,22 @@ struct SpillAcc {
 
 // Marginal histograms: low value and value sum per pair, degree-weighted value per pixel.
 struct MargAcc {
+    // this lane's copy of each table (copy c of entry j at word j * copies + c)
     lds_u32 *hmin, *hdeg, *hsum;
     __device__ __forceinline__ void pair(uint32_t x, uint32_t y, bool valid) {
         if (valid) {
-            lds_inc(&hmin[min(x, y)]);
-            lds_inc(&hsum[x + y]);
+            lds_inc(hmin + (min(x, y) << cs));
+            lds_inc(hsum + ((x + y) << cs));
         }
     }
     __device__ __forceinline__ void pixel(uint32_t v, uint32_t deg, bool valid) {
-        if (valid) lds_add(&hdeg[v], deg);
+        if (valid) lds_add(hdeg + (v << cs), deg);
     }
     static constexpr bool kPixels = true;
     static constexpr bool kSpill = false;
     static constexpr uint32_t kScale = 1;
     uint32_t dmax, nb;
+    uint32_t cs = 0;  // log2 of the table copies
     __device__ __forceinline__ bool needs_spill() const { return false; }
     typedef uint32_t P;
     __device__ static __forceinline__ P prep(uint32_t v) { return v; }
@@ -821,11 +760,11 @@ __device__ __forceinline__ uint64_t add_levels(int64_t *acc, int M, bool packed,
 }
 
 // E[v] for v >= 1 from the marginals at v-1: hmin + hmax - hsum[2v-3] - 2 hsum[2v-2] - hsum[2v-1].
-__device__ __forceinline__ int64_t second_diff(int64_t lohi, const lds_u32 *hsum, int v, int M) {
+__device__ __forceinline__ int64_t second_diff(int64_t lohi, const lds_u32 *hsum, int v, int M, int st = 1) {
     const int s = 2 * v - 2;
-    int64_t e = lohi - 2 * (int64_t)hsum[s];
-    if (s >= 1) e -= hsum[s - 1];
-    if (s + 1 <= 2 * M - 2) e -= hsum[s + 1];
+    int64_t e = lohi - 2 * (int64_t)hsum[s * st];
+    if (s >= 1) e -= hsum[(s - 1) * st];
+    if (s + 1 <= 2 * M - 2) e -= hsum[(s + 1) * st];
     return e;
 }
 
@@ -978,13 +917,22 @@ __device__ __forceinline__ uint64_t merge_tri(const KParams &p, lds_u32 *lds, in
 }
 
 __device__ __forceinline__ uint64_t merge_marg(const KParams &p, lds_u32 *lds, int64_t *acc) {
-    const int M = p.M;
-    const lds_u32 *hmin = lds, *hdeg = lds + M, *hsum = lds + 2 * M;
+    const int M = p.M, C = p.copies;
+    if (C > 1) {
+        // the copies of each entry summed into its first word (every entry by one thread)
+        for (int j = threadIdx.x; j < 4 * M; j += blockDim.x) {
+            uint32_t sum = 0;
+            for (int c = 0; c < C; ++c) sum += lds[j * C + c];
+            lds[j * C] = sum;
+        }
+        __syncthreads();
+    }
+    const lds_u32 *hmin = lds, *hdeg = lds + M * C, *hsum = lds + 2 * M * C;
     phase_stamp(3);
     uint64_t sink = 0;
     for (int v = threadIdx.x; v < M; v += blockDim.x) {
-        const int64_t d1 = 2 * (int64_t)hmin[v] - (int64_t)hdeg[v];
-        const int64_t e = v >= 1 ? second_diff((int64_t)hdeg[v - 1], hsum, v, M) : 0;
+        const int64_t d1 = 2 * (int64_t)hmin[v * C] - (int64_t)hdeg[v * C];
+        const int64_t e = v >= 1 ? second_diff((int64_t)hdeg[(v - 1) * C], hsum, v, M, C) : 0;
         sink ^= add_levels(acc, M, p.packed_acc != 0, v, d1, e);
     }
     return sink;
@@ -1261,10 +1209,49 @@ __device__ __forceinline__ void finalize_small(const KParams &p, int i, lds_u32 
 // finalize: prefix sums, C, local maxima and t0 for the image with output index i (run by one
 // workgroup)
 //
-// LDS use (the histogram tables are dead by now): two int64 arrays of blockDim + 1 entries holding
-// the current chunk's (sum, count) shifted by one, so each thread sees its left neighbour, then one
-// byte per threshold: bits 0-1 = sign of C(t) - C(t-1) (0 equal, 1 rise, 2 fall), bit 2 = C(t) > 0.
+// LDS use (the histogram tables are dead by now): one byte per threshold from address 0: bits 0-1 =
+// sign of C(t) - C(t-1) (0 equal, 1 rise, 2 fall), bit 2 = C(t) > 0; from fin_gather_offset the
+// replica sums of the levels (packed accumulators).
 
+// Exclusive prefix sums of three values over the workgroup (all threads, blockDim.x a multiple of 64,
+// at most 1024), and their totals; the barriers order LDS only, so global stores issued before stay
+// in flight.
+__device__ __forceinline__ void block_exscan3(int64_t (&x)[3], LdsScratch &bs, int64_t (&total)[3]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int64_t inc[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) inc[q] = wave_iscan(x[q]);
+    if (lane == 63) {
+        bs.scan[wid] = inc[0];
+        bs.red_s[wid] = inc[1];
+        bs.red_k[wid] = inc[2];
+    }
+    lds_barrier();
+    int64_t before[3] = {0, 0, 0}, all[3] = {0, 0, 0};
+    for (int w = 0; w < nw; ++w) {
+        const int64_t a = bs.scan[w], b = bs.red_s[w], c = bs.red_k[w];
+        if (w < wid) {
+            before[0] += a;
+            before[1] += b;
+            before[2] += c;
+        }
+        all[0] += a;
+        all[1] += b;
+        all[2] += c;
+    }
+    lds_barrier();  // every wave has read the totals before the scratch is written again
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        x[q] = before[q] + inc[q] - x[q];
+        total[q] = all[q];
+    }
+}
+
+// The finishing step for M > 256 (the whole workgroup): thread j takes the L = ceil(M / blockDim)
+// consecutive levels [j L, j L + L). One pass forms its totals of D1, E and v E, one workgroup scan
+// gives the prefixes before its levels, a second pass gives count, sum and C of each level and the
+// sign of C(t) - C(t - 1) (the level before its first comes from the prefix itself); the local
+// maxima are counted per thread and placed in ascending order by a second scan.
 __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, LdsScratch &bs) {
     const int M = p.M, tid = threadIdx.x, nt = blockDim.x;
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(p.acc + (int64_t)i * p.acc_stride);
@@ -1273,108 +1260,125 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
     int64_t *osum = p.sum + (int64_t)i * p.ostride;
     int64_t *ocnt = p.count + (int64_t)i * p.ostride;
     double *oC = p.C + (int64_t)i * p.ostride;
-    KOHLER_LDS int64_t *csum = reinterpret_cast<KOHLER_LDS int64_t *>(lds);
-    KOHLER_LDS int64_t *ccnt = csum + (nt + 1);
-    KOHLER_LDS uint8_t *flags = reinterpret_cast<KOHLER_LDS uint8_t *>(ccnt + (nt + 1));
+    KOHLER_LDS uint8_t *flags = reinterpret_cast<KOHLER_LDS uint8_t *>(lds);  // M bytes
+    // the replica sums of every level (packed accumulators), gathered before the scans
+    KOHLER_LDS uint64_t *gsum = reinterpret_cast<KOHLER_LDS uint64_t *>(
+        reinterpret_cast<KOHLER_LDS uint8_t *>(lds) + fin_gather_offset(M, nt));
+    const bool packed = p.packed_acc != 0;
 
     // the range flag is fetched now, with the accumulators, and used at the very end
     uint32_t rf = 0;
     if (tid == 0) rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
+    phase_stamp(6);
 
-    // With P0(t) = sum_{v<=t} E[v] and P1(t) = sum_{v<=t} v E[v], the double prefix sum of E is
-    // sum(t) = (t + 1) P0(t) - P1(t), so count and sum come out of one three-way scan. (int64
-    // arithmetic wraps, but the result is exact because sum(t) itself fits.)
-    const bool one_chunk = M <= nt;  // then the results stay in registers until the end
-    int64_t car[3] = {0, 0, 0}, tot[3], prev_s = 0, prev_k = 0, keep_s = 0, keep_k = 0;
+    // Packed accumulators: every level's replica sum into LDS first, kFinGather levels per thread
+    // with all their loads in flight (indices clamped, the surplus dropped): about R memory
+    // latencies in all.
+    if (packed) {
+        constexpr int kFinGather = 8;
+        for (int b = 0; b < M; b += kFinGather * nt) {
+            uint64_t sum[kFinGather];
+#pragma unroll
+            for (int k = 0; k < kFinGather; ++k) sum[k] = 0;
+            for (int r = 0; r < R; ++r) {
+                uint64_t v[kFinGather];
+#pragma unroll
+                for (int k = 0; k < kFinGather; ++k) v[k] = load_shared(acc + r * RS + min(b + k * nt + tid, M - 1));
+#pragma unroll
+                for (int k = 0; k < kFinGather; ++k) sum[k] += v[k];
+            }
+#pragma unroll
+            for (int k = 0; k < kFinGather; ++k)
+                if (b + k * nt + tid < M) gsum[b + k * nt + tid] = sum[k];
+        }
+        lds_barrier();
+    }
+    // D1 and E of level t: from the gathered sums (E * 2^32 + D1 in one word, |D1| < 2^31 because
+    // the image has < 2^30 pairs), else summed from the replicas' two words (images with 2^30 or
+    // more pairs)
+    auto level = [&](int t, int64_t &d1, int64_t &e) {
+        if (packed) {
+            const uint64_t w = gsum[t];
+            d1 = (int64_t)(int32_t)(uint32_t)w;
+            e = (int64_t)(w - (uint64_t)d1) >> 32;
+        } else {
+            uint64_t w0 = 0, w1 = 0;
+            for (int r = 0; r < R; ++r) {
+                w0 += load_shared(acc + r * RS + t);
+                w1 += load_shared(acc + r * RS + M + t);
+            }
+            d1 = (int64_t)w0;
+            e = (int64_t)w1;
+        }
+    };
+    const int L = (M + nt - 1) / nt;
+    const int lo = min(M, tid * L), hi = min(M, lo + L);
+
+    // 1. this thread's totals, then the prefixes before its levels. With P0(t) = sum_{v<=t} E[v]
+    //    and P1(t) = sum_{v<=t} v E[v], the double prefix sum of E is sum(t) = (t + 1) P0(t) - P1(t)
+    //    (int64 arithmetic wraps, but the result is exact because sum(t) itself fits).
+    int64_t x[3] = {0, 0, 0}, tot[3];
+    for (int t = lo; t < hi; ++t) {
+        int64_t d1, e;
+        level(t, d1, e);
+        x[0] += d1;
+        x[1] += e;
+        x[2] += (int64_t)t * e;
+    }
+    block_exscan3(x, bs, tot);
+
+    // 2. count, sum and C per level; flags: bit 0 rise, bit 1 fall (against level t - 1), bit 2 C > 0
+    int64_t cnt = x[0], P0 = x[1], P1 = x[2];
+    int64_t ps = (int64_t)lo * P0 - P1, pk = cnt;  // level lo - 1
     int32_t bt = -1;
     int64_t bsum = 0, bcnt = 0;
-    for (int b = 0; b < M; b += nt) {
-        const int t = b + tid;
-        const bool in = t < M;
-        int64_t d1 = 0, e = 0;
-        if (in) {
-            // sum the replicas (the packed form is linear, so packed words add up as well); all
-            // loads are issued before any is used (replica indices past R re-read the last one
-            // and are dropped), so the sum costs one memory latency, not R
-            uint64_t v0[kMaxReplicas], v1[kMaxReplicas];
-#pragma unroll
-            for (int r = 0; r < kMaxReplicas; ++r) v0[r] = load_shared(acc + min(r, R - 1) * RS + t);
-            if (!p.packed_acc) {
-#pragma unroll
-                for (int r = 0; r < kMaxReplicas; ++r) v1[r] = load_shared(acc + min(r, R - 1) * RS + M + t);
-            }
-            uint64_t w0 = 0, w1 = 0;
-#pragma unroll
-            for (int r = 0; r < kMaxReplicas; ++r) {
-                w0 += r < R ? v0[r] : 0;
-                if (!p.packed_acc) w1 += r < R ? v1[r] : 0;
-            }
-            if (p.packed_acc) {
-                d1 = (int64_t)(int32_t)(uint32_t)w0;
-                e = (int64_t)(w0 - (uint64_t)d1) >> 32;
-            } else {
-                d1 = (int64_t)w0;
-                e = (int64_t)w1;
-            }
-        }
-        int64_t x[3] = {d1, e, (int64_t)t * e};
-        block_scan3(x, bs, tot);
-        const int64_t cnt = car[0] + x[0];
-        const int64_t P0 = car[1] + x[1], P1 = car[2] + x[2];
+    for (int t = lo; t < hi; ++t) {
+        int64_t d1, e;
+        level(t, d1, e);
+        cnt += d1;
+        P0 += e;
+        P1 += (int64_t)t * e;
         const int64_t sm = (int64_t)(t + 1) * P0 - P1;
-#pragma unroll
-        for (int q = 0; q < 3; ++q) car[q] += tot[q];
-        if (tid == 0) {
-            csum[0] = prev_s;
-            ccnt[0] = prev_k;
+        osum[t] = sm;
+        ocnt[t] = cnt;
+        oC[t] = cnt ? (double)sm / (double)cnt : 0.0;
+        const int r = (t == 0) ? 0 : cmp_curve(sm, cnt, ps, pk);
+        const int pos = cmp_curve(sm, cnt, 0, 1) > 0;
+        flags[t] = (uint8_t)((r > 0 ? 1 : (r < 0 ? 2 : 0)) | (pos ? 4 : 0));
+        if (bt < 0 || cmp_curve(sm, cnt, bsum, bcnt) > 0) {
+            bt = t;
+            bsum = sm;
+            bcnt = cnt;
         }
-        csum[tid + 1] = sm;
-        ccnt[tid + 1] = cnt;
-        __syncthreads();
-        if (in) {
-            if (one_chunk) {
-                keep_s = sm;
-                keep_k = cnt;
-            } else {
-                osum[t] = sm;
-                ocnt[t] = cnt;
-                oC[t] = cnt ? (double)sm / (double)cnt : 0.0;
-            }
-            const int r = (t == 0) ? 0 : cmp_curve(sm, cnt, csum[tid], ccnt[tid]);
-            const int pos = cmp_curve(sm, cnt, 0, 1) > 0;
-            flags[t] = (uint8_t)((r > 0 ? 1 : (r < 0 ? 2 : 0)) | (pos ? 4 : 0));
-            if (bt < 0 || cmp_curve(sm, cnt, bsum, bcnt) > 0) {
-                bt = t;
-                bsum = sm;
-                bcnt = cnt;
-            }
-        }
-        prev_s = csum[nt];
-        prev_k = ccnt[nt];
+        ps = sm;
+        pk = cnt;
     }
-    __syncthreads();
+    lds_barrier();
+    clock_stamp(12);
 
-    // local maxima: a run start (t == 0 or a rise) with positive C whose run ends in a fall or at M
+    // 3. local maxima: a run start (t == 0 or a rise) with positive C whose run ends in a fall or
+    //    at M; this thread's are written after those of the threads before it
+    auto is_max = [&](int t) -> bool {
+        const uint32_t f = flags[t];
+        if (!((f & 4u) && (t == 0 || (f & 3u) == 1u))) return false;
+        int u = t + 1;
+        while (u < M && (flags[u] & 3u) == 0u) ++u;
+        return u == M || (flags[u] & 3u) == 2u;
+    };
+    int64_t y[3] = {0, 0, 0}, ytot[3];
+    for (int t = lo; t < hi; ++t) y[0] += is_max(t) ? 1 : 0;
+    block_exscan3(y, bs, ytot);
     int32_t *othr = p.thr + (int64_t)i * p.thr_stride;
-    int64_t found = 0;
-    for (int b = 0; b < M; b += nt) {
-        const int t = b + tid;
-        int64_t flag = 0;
-        if (t < M) {
-            const uint32_t f = flags[t];
-            if ((f & 4u) && (t == 0 || (f & 3u) == 1u)) {
-                int u = t + 1;
-                while (u < M && (flags[u] & 3u) == 0u) ++u;
-                flag = (u == M || (flags[u] & 3u) == 2u) ? 1 : 0;
-            }
+    int64_t posn = y[0];
+    for (int t = lo; t < hi; ++t)
+        if (is_max(t)) {
+            if (posn < p.cap) othr[posn] = t;
+            ++posn;
         }
-        int64_t ftot;
-        const int64_t pos = found + block_scan(flag, bs, ftot) - flag;
-        if (flag && pos < p.cap) othr[pos] = t;
-        found += ftot;
-    }
+    const int64_t found = ytot[0];
+    clock_stamp(13);
 
-    // t0: smallest t attaining max C (each thread's candidate is the first maximum of its own t's)
+    // 4. t0: smallest t attaining max C (each thread's candidate is the first maximum of its levels)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const int32_t ot = __shfl_down(bt, off, 64);
@@ -1394,7 +1398,8 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
         bs.red_s[tid >> 6] = bsum;
         bs.red_k[tid >> 6] = bcnt;
     }
-    __syncthreads();
+    lds_barrier();
+    clock_stamp(14);
     if (tid == 0) {
         int32_t t0 = -1;
         int64_t s0 = 0, k0 = 0;
@@ -1415,18 +1420,14 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
         p.t0[(int64_t)i * p.istride] = t0;
         p.status[(int64_t)i * p.istride] = rf ? ST_RANGE : (found > p.cap ? ST_CAPACITY : ST_OK);
     }
-    // stores last, after every barrier, so that no barrier waits for them
-    if (one_chunk && tid < M) {
-        osum[tid] = keep_s;
-        ocnt[tid] = keep_k;
-        oC[tid] = keep_k ? (double)keep_s / (double)keep_k : 0.0;
-    }
+    // the replicas cleared for the next launch
     for (int t = tid; t < M; t += nt) {
         for (int r = 0; r < R; ++r) {
             store_shared(acc + r * RS + t, 0);
-            if (!p.packed_acc) store_shared(acc + r * RS + M + t, 0);
+            if (!packed) store_shared(acc + r * RS + M + t, 0);
         }
     }
+    phase_stamp(7);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1562,7 +1563,7 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
     if constexpr (FORM == FORM_BAND)
         table_words = ((uint32_t)p.copies * ((uint32_t)p.band + 2u) * kRowStride + 768u + 3u) & ~3u;
     else if constexpr (FORM == FORM_TRI) table_words = (tri_words((uint32_t)p.M) + 64u + 3u) & ~3u;
-    else table_words = 4u * (uint32_t)p.M;
+    else table_words = 4u * (uint32_t)p.M * (uint32_t)p.copies;
 
     auto clear_tables = [&]() { clear_lds(lds, bs, table_words); };
 
@@ -1586,7 +1587,10 @@ __global__ void __launch_bounds__((max_block<NB, K, FORM>())) curve_kernel(KPara
             SpillAcc spill{0u, 0u, 0u};  // not used by the triangular form
             chunks(acc, spill, vmax, Mm1);
         } else {
-            MargAcc acc{lds, lds + p.M, lds + 2 * p.M, 0u, 0u};
+            // lane l adds to copy l % copies (1 or 2) of each table
+            const uint32_t nc = (uint32_t)p.copies, cl = (threadIdx.x & 63u) & (nc - 1u);
+            const uint32_t Mc = (uint32_t)p.M * nc;
+            MargAcc acc{lds + cl, lds + Mc + cl, lds + 2u * Mc + cl, 0u, 0u, nc == 2u ? 1u : 0u};
             SpillAcc spill{0u, 0u, 0u};  // not used by the marginal form
             chunks(acc, spill, vmax, Mm1);
         }

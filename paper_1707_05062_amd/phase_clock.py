@@ -5,8 +5,10 @@ Build it first on the CPU (``python -m paper_1707_05062_amd.build --phase-clock`
 records the 100 MHz real-time counter at its phase boundaries (entry, LDS tables cleared, pair work
 done, merge atomics issued, merge atomics performed, ticket taken; the finishing workgroup also after
 gathering the accumulator replicas and at its end) and each wave the end of its pair work. The script
-launches the kernel on the 3456x5184 u8 image (M = 256, N4) over rotated buffers, reads the stamps
-after each launch and prints a Markdown summary (medians over the launches, in microseconds).
+launches the kernel on the 3456x5184 u8 image (M = 256, N4), or the 4096x4096 12-bit image (M = 4096,
+N4 or N8), over rotated buffers, reads the stamps after each launch and prints a Markdown summary
+(medians over the launches, in microseconds). For M > 256 the finishing workgroup sums the replicas
+level block by level block inside its scan, so its gather time is part of its finish.
 """
 from __future__ import annotations
 
@@ -71,6 +73,9 @@ def main():
     ap.add_argument("--launches", type=int, default=30)
     ap.add_argument("--rotate", type=int, default=32)
     ap.add_argument("--lib", default="", help="another measurement build of the library (default: libkohler_phase.so)")
+    ap.add_argument("--workload", choices=["18mp", "c3n4", "c3n8"], default="18mp",
+                    help="18mp: the 3456x5184 u8 image, M=256, N4; c3n4 / c3n8: the 4096x4096 12-bit image, "
+                         "M=4096, N4 / N8")
     args = ap.parse_args()
 
     import torch
@@ -86,30 +91,34 @@ def main():
     lib.kohler_phase_clock_read.restype = ctypes.c_int
     keys = ("form", "band", "block", "grid", "px_per_lane", "replicas", "copies")
     plan = dict(zip(keys, (int(x) for x in args.plan.split(":"))))
-    img = gen.cfg2_image()
+    if args.workload == "18mp":
+        img, dt, M, nb = gen.cfg2_image(), _lib.U8, 256, 4
+    else:
+        img, dt, M, nb = gen.cfg3_image(), _lib.U16, 4096, int(args.workload[-1])
     H, W = img.shape
-    ctx.set_plan(_lib.U8, 256, 4, **plan)
-    used = ctx.get_plan(_lib.U8, H, W, 256, 4)
+    ctx.set_plan(dt, M, nb, **plan)
+    used = ctx.get_plan(dt, H, W, M, nb)
     dev = torch.device("cuda", 0)
-    src = torch.from_numpy(img).to(dev)
-    bufs = [src.clone() for _ in range(args.rotate)]
-    out = ctx.alloc_outputs(256, 256)
+    src = (torch.from_numpy(img.view(np.int16)).to(dev).view(torch.uint16) if img.dtype == np.uint16
+           else torch.from_numpy(img).to(dev))
+    bufs = [src.clone() for _ in range(min(args.rotate, 8 if img.dtype == np.uint16 else args.rotate))]
+    out = ctx.alloc_outputs(M, M)
     slots = np.zeros(MAXWG * SLOTS, np.uint64)
     waves = np.zeros(MAXWG * WAVES, np.uint64)
     for i in range(10):
-        ctx.curve_async(bufs[i % len(bufs)], 256, 4, out=out)
+        ctx.curve_async(bufs[i % len(bufs)], M, nb, out=out)
     torch.cuda.synchronize()
     rows = []
     for i in range(args.launches):
         assert lib.kohler_phase_clock_read(None, None, 1) == 0
-        ctx.curve_async(bufs[(10 + i) % len(bufs)], 256, 4, out=out)
+        ctx.curve_async(bufs[(10 + i) % len(bufs)], M, nb, out=out)
         torch.cuda.synchronize()
         assert lib.kohler_phase_clock_read(slots.ctypes.data, waves.ctypes.data, 0) == 0
         rows.append(breakdown(slots, waves, used["grid"], used["block"] // 64))
         print(f"launch {i}: span {rows[-1]['span']:.2f} us", file=sys.stderr, flush=True)
     assert int(out["ints"][2]) == 0
     med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
-    print(f"plan {used}; {args.launches} launches of the {H}x{W} u8 image (M=256, N4); "
+    print(f"plan {used}; {args.launches} launches of the {H}x{W} {img.dtype} image (M={M}, N{nb}); "
           "medians over launches, microseconds")
     print("| quantity | us |\n|---|---|")
     for k, v in med.items():

@@ -88,7 +88,9 @@ def test_reduces_to_main_kernel(ctx):
             assert np.array_equal(a.C, b.C) and list(a.thresholds) == list(b.thresholds) and a.t0 == b.t0
 
 
-@pytest.mark.parametrize("shape", [(1, 1000), (1000, 1), (37, 301), (64, 512), (17, 1025), (129, 513)])
+# (60, 1600): interior tiles (every neighbour of every pixel inside the image, pairs taken without
+# tests) next to border tiles on all four sides, for every radius up to 7
+@pytest.mark.parametrize("shape", [(1, 1000), (1000, 1), (37, 301), (64, 512), (17, 1025), (129, 513), (60, 1600)])
 def test_ragged_u8(ctx, shape):
     rng = np.random.default_rng(sum(shape))
     for kind in ("uniform", "smooth"):

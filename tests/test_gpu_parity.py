@@ -130,7 +130,7 @@ def test_plan_sweep(ctx, K):
                     for ppl in (4, 8):
                         plans.append((form, band, block, grid, ppl))
         for form, band, block, grid, ppl in plans:
-            for copies in ((1, 2, 4) if form == K.FORM_BAND else (0,)):
+            for copies in ((1, 2, 4) if form == K.FORM_BAND else (1, 2) if form == K.FORM_MARG else (0,)):
                 if copies * (band + 2) * 272 * 4 + 768 * 4 + 512 > 160 * 1024:
                     continue  # the tables would not fit the LDS: the plan is refused
                 ctx.set_plan(1, 256, nbhd, form=form, band=band, block=block, grid=grid, px_per_lane=ppl,
@@ -348,6 +348,26 @@ def test_batch_u16(ctx):
     imgs = [gen.random_image(rng, int(rng.integers(1, 70)), int(rng.integers(1, 600)), 4096, np.uint16,
                              "smooth") for _ in range(9)]
     _batch_check(ctx, imgs, 4096, 8)
+
+
+@pytest.mark.parametrize("nbhd", [4, 8])
+def test_marginal_copies_u16(ctx, K, nbhd):
+    """The marginal form with one and two interleaved table copies (12-bit levels: 2 x 64 KB of
+    tables), single image and batch, over workgroup sizes and grids; the copies are summed before
+    the merge, so every plan gives the same result."""
+    rng = np.random.default_rng(90 + nbhd)
+    img = gen.random_image(rng, 129, 1100, 4096, np.uint16, "smooth")
+    img[40:60, 100:700] = rng.integers(0, 4096, size=(20, 600))
+    dev = to_device(img)
+    ref = reference(img, 4096, nbhd)
+    for copies in (1, 2):
+        for block, grid in [(256, 1), (512, 3), (512, 0)]:
+            ctx.set_plan(2, 4096, nbhd, form=K.FORM_MARG, block=block, grid=grid, copies=copies)
+            assert_result(ctx.curve(dev, 4096, nbhd), ref, what=f"marg c{copies} b{block} g{grid} N{nbhd}")
+        _batch_check(ctx, [img, gen.random_image(rng, 7, 300, 4096, np.uint16, "uniform")], 4096, nbhd)
+    with pytest.raises(K.KohlerError):  # four copies of the marginal tables are refused
+        ctx.set_plan(2, 4096, nbhd, form=K.FORM_MARG, copies=4)
+    ctx.set_plan(2, 4096, nbhd)
 
 
 # ----------------------------------------------------------------------------------------------
