@@ -98,7 +98,8 @@ constexpr int kMaxBandCopies = 4;
 // is larger; 16-byte aligned. Finalize for M <= 256 needs 8 KiB (the curve and per-wave masks); for
 // larger M, two int64 arrays of block + 1 entries and one byte per grey level.
 // Finishing step for M > 256: M flag bytes (within the first 16 (block + 1) + M bytes), then (from
-// this byte offset) the replica sums of the M levels, one uint64 each.
+// this byte offset) the replica sums of the M levels, one uint64 each, in ceil(M / block) rows of
+// block words (thread j's levels in column j).
 __host__ __device__ inline size_t fin_gather_offset(int M, int block) {
     return (16 * ((size_t)block + 1) + (size_t)M + 15) & ~(size_t)15;
 }
@@ -111,7 +112,8 @@ __host__ __device__ inline size_t lds_main_bytes(int form, int M, int band, int 
                          : (form == FORM_TRI) ? (size_t)M * (M + 1) / 2 + 64 + 4 * (size_t)M
                                               : 4 * (size_t)M * (size_t)copies;
     const size_t table = (words * 4 + 15) & ~(size_t)15;
-    const size_t fin = M <= 256 ? (size_t)8192 : fin_gather_offset(M, block) + 8 * (size_t)M;
+    const size_t fin = M <= 256 ? (size_t)8192
+                                : fin_gather_offset(M, block) + 8 * (((size_t)M + block - 1) / block) * (size_t)block;
     return table > fin ? table : fin;
 }
 

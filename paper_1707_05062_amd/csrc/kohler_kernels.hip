@@ -1270,9 +1270,12 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
     uint32_t rf = 0;
     if (tid == 0) rf = __hip_atomic_load(gptr(p.rflag + i), __ATOMIC_RELAXED, KOHLER_XSCOPE);
     phase_stamp(6);
+    // this thread's levels [lo, hi)
+    const int L = (M + nt - 1) / nt;
+    const int lo = min(M, tid * L), hi = min(M, lo + L);
 
     // Packed accumulators: every level's replica sum into LDS first, kFinGather levels per thread
-    // with all their loads in flight (indices clamped, the surplus dropped): about R memory
+    // with all their loads in flight (indices clamped, the surplus dropped): about R / 2 memory
     // latencies in all.
     if (packed) {
         constexpr int kFinGather = 8;
@@ -1280,16 +1283,22 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
             uint64_t sum[kFinGather];
 #pragma unroll
             for (int k = 0; k < kFinGather; ++k) sum[k] = 0;
-            for (int r = 0; r < R; ++r) {
-                uint64_t v[kFinGather];
+            for (int r = 0; r < R; r += 2) {  // two replicas per round (the second clamped, dropped past R)
+                const int r2 = min(r + 1, R - 1);
+                uint64_t v[kFinGather], w[kFinGather];
 #pragma unroll
-                for (int k = 0; k < kFinGather; ++k) v[k] = load_shared(acc + r * RS + min(b + k * nt + tid, M - 1));
+                for (int k = 0; k < kFinGather; ++k) {
+                    v[k] = load_shared(acc + r * RS + min(b + k * nt + tid, M - 1));
+                    w[k] = load_shared(acc + r2 * RS + min(b + k * nt + tid, M - 1));
+                }
 #pragma unroll
-                for (int k = 0; k < kFinGather; ++k) sum[k] += v[k];
+                for (int k = 0; k < kFinGather; ++k) sum[k] += v[k] + (r + 1 < R ? w[k] : 0ull);
             }
 #pragma unroll
-            for (int k = 0; k < kFinGather; ++k)
-                if (b + k * nt + tid < M) gsum[b + k * nt + tid] = sum[k];
+            for (int k = 0; k < kFinGather; ++k) {
+                const int t = b + k * nt + tid;
+                if (t < M) gsum[(t % L) * nt + t / L] = sum[k];  // level j L + q of thread j at q nt + j
+            }
         }
         lds_barrier();
     }
@@ -1298,7 +1307,7 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
     // more pairs)
     auto level = [&](int t, int64_t &d1, int64_t &e) {
         if (packed) {
-            const uint64_t w = gsum[t];
+            const uint64_t w = gsum[(t - lo) * nt + tid];  // consecutive threads, consecutive words
             d1 = (int64_t)(int32_t)(uint32_t)w;
             e = (int64_t)(w - (uint64_t)d1) >> 32;
         } else {
@@ -1311,8 +1320,6 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
             e = (int64_t)w1;
         }
     };
-    const int L = (M + nt - 1) / nt;
-    const int lo = min(M, tid * L), hi = min(M, lo + L);
 
     // 1. this thread's totals, then the prefixes before its levels. With P0(t) = sum_{v<=t} E[v]
     //    and P1(t) = sum_{v<=t} v E[v], the double prefix sum of E is sum(t) = (t + 1) P0(t) - P1(t)
@@ -1328,10 +1335,14 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
     block_exscan3(x, bs, tot);
 
     // 2. count, sum and C per level; flags: bit 0 rise, bit 1 fall (against level t - 1), bit 2 C > 0
+    //    Orders are taken on the rounded C first: rounding is monotonic, so different doubles
+    //    order the exact quotients the same way; equal doubles are settled by the exact compare.
     int64_t cnt = x[0], P0 = x[1], P1 = x[2];
     int64_t ps = (int64_t)lo * P0 - P1, pk = cnt;  // level lo - 1
+    double pC = pk ? (double)ps / (double)pk : 0.0;
     int32_t bt = -1;
     int64_t bsum = 0, bcnt = 0;
+    double bC = 0.0;
     for (int t = lo; t < hi; ++t) {
         int64_t d1, e;
         level(t, d1, e);
@@ -1339,19 +1350,26 @@ __device__ __forceinline__ void finalize(const KParams &p, int i, lds_u32 *lds, 
         P0 += e;
         P1 += (int64_t)t * e;
         const int64_t sm = (int64_t)(t + 1) * P0 - P1;
+        const double C = cnt ? (double)sm / (double)cnt : 0.0;
         osum[t] = sm;
         ocnt[t] = cnt;
-        oC[t] = cnt ? (double)sm / (double)cnt : 0.0;
-        const int r = (t == 0) ? 0 : cmp_curve(sm, cnt, ps, pk);
-        const int pos = cmp_curve(sm, cnt, 0, 1) > 0;
+        oC[t] = C;
+        int r = 0;
+        if (t > 0) {
+            r = C > pC ? 1 : (C < pC ? -1 : 0);
+            if (r == 0) r = cmp_curve(sm, cnt, ps, pk);
+        }
+        const bool pos = cnt > 0 && sm > 0;  // C(t) > 0
         flags[t] = (uint8_t)((r > 0 ? 1 : (r < 0 ? 2 : 0)) | (pos ? 4 : 0));
-        if (bt < 0 || cmp_curve(sm, cnt, bsum, bcnt) > 0) {
+        if (bt < 0 || C > bC || (C == bC && cmp_curve(sm, cnt, bsum, bcnt) > 0)) {
             bt = t;
             bsum = sm;
             bcnt = cnt;
+            bC = C;
         }
         ps = sm;
         pk = cnt;
+        pC = C;
     }
     lds_barrier();
     clock_stamp(12);
