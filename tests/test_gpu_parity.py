@@ -67,6 +67,24 @@ def test_tiny_u16_large_m(ctx):
                 assert_result(res, reference(img, M, nbhd), what=f"u16 {H}x{W} M={M} N{nbhd}")
 
 
+@pytest.mark.parametrize("block", [256, 512])
+def test_large_m_finish_blocks(ctx, K, block):
+    """The finishing step for M > 256: each thread takes ceil(M / block) consecutive levels, so the
+    last threads get fewer or none (M = 257, 300, 513, 1000, 1025, 3000 against 256 and 512
+    threads), with packed and with two-word accumulators, single image and batch."""
+    rng = np.random.default_rng(block)
+    img0 = gen.random_image(rng, 61, 333, 3000, np.uint16, "smooth")
+    for M in (257, 300, 513, 1000, 1025, 3000):
+        img = np.minimum(img0, M - 1).astype(np.uint16)
+        img[10:20, 40:200] = rng.integers(0, M, size=(10, 160))
+        ref = reference(img, M, 4)
+        for split in (0, 1):
+            ctx.set_plan(2, M, 4, form=K.FORM_MARG, block=block, grid=5, acc_split=split)
+            assert_result(ctx.curve(to_device(img), M, 4), ref, what=f"M={M} block {block} split {split}")
+        _batch_check(ctx, [img, gen.random_image(rng, 9, 70, M, np.uint16, "uniform")], M, 4)
+        ctx.set_plan(2, M, 4)
+
+
 # ----------------------------------------------------------------------------------------------
 # multi-strip images with ragged tails
 
