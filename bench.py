@@ -187,7 +187,7 @@ def headline(args, K, ctx, torch, gen) -> tuple[dict, np.ndarray]:
         ctx.set_plan(_lib.U8, M, nbhd, **parse_plan(args.plan))
         tuned = {"source": "--plan"}
     else:
-        plan, us = ctx.autotune([bufs[0]], M, nbhd, reps=5)
+        plan, us = ctx.autotune([bufs[0]], M, nbhd, reps=15)  # medians of 15 launches: a steadier pick
         tuned = {"source": "autotuner", "plan": plan, "median_us": us}
         log(f"autotuned plan {plan} {us:.2f} us")
     outs = ctx.alloc_outputs(M, M)
