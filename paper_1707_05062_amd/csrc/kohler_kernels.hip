@@ -1836,11 +1836,14 @@ __global__ void __launch_bounds__(kNbBlock) nbhd_kernel(NbParams q) {
         if (blockIdx.x == 0 && threadIdx.x == 0) p.status[(int64_t)p.img0.out * p.istride] = ST_LAYOUT;
         return;
     }
+    phase_stamp(0);
+    phase_place();
     const int G = gridDim.x;
     const int g = (G % 8 == 0) ? (int)(blockIdx.x % 8) * (G / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
     const uint32_t Mm1 = (uint32_t)p.M - 1u;
     const uint32_t table_words = FORM == FORM_TRI ? (tri_words((uint32_t)p.M) + 64u + 3u) & ~3u : 4u * (uint32_t)p.M;
     clear_lds(lds, bs, table_words);
+    phase_stamp(1);
 
     const KImage im = image_desc(p, 0);
     const int64_t H = im.H, W = im.W;
@@ -2003,6 +2006,7 @@ __global__ void __launch_bounds__(kNbBlock) nbhd_kernel(NbParams q) {
         else pass(std::false_type{});
         __syncthreads();  // before the next tile is staged over this one
     }
+    phase_wave_stamp();
     flush_image<FORM, CLAMP>(p, lds, bs, im, vmax, mine, q.tiles);
 }
 

@@ -73,9 +73,10 @@ def main():
     ap.add_argument("--launches", type=int, default=30)
     ap.add_argument("--rotate", type=int, default=32)
     ap.add_argument("--lib", default="", help="another measurement build of the library (default: libkohler_phase.so)")
-    ap.add_argument("--workload", choices=["18mp", "c3n4", "c3n8"], default="18mp",
+    ap.add_argument("--workload", choices=["18mp", "c3n4", "c3n8", "nbhd18mp"], default="18mp",
                     help="18mp: the 3456x5184 u8 image, M=256, N4; c3n4 / c3n8: the 4096x4096 12-bit image, "
-                         "M=4096, N4 / N8")
+                         "M=4096, N4 / N8; nbhd18mp: the 18 MP image through the neighbourhood kernel (N4 "
+                         "given by its half offsets; --plan is ignored)")
     args = ap.parse_args()
 
     import torch
@@ -91,13 +92,23 @@ def main():
     lib.kohler_phase_clock_read.restype = ctypes.c_int
     keys = ("form", "band", "block", "grid", "px_per_lane", "replicas", "copies")
     plan = dict(zip(keys, (int(x) for x in args.plan.split(":"))))
-    if args.workload == "18mp":
+    nbhd_path = args.workload == "nbhd18mp"
+    if args.workload in ("18mp", "nbhd18mp"):
         img, dt, M, nb = gen.cfg2_image(), _lib.U8, 256, 4
     else:
         img, dt, M, nb = gen.cfg3_image(), _lib.U16, 4096, int(args.workload[-1])
     H, W = img.shape
-    ctx.set_plan(dt, M, nb, **plan)
-    used = ctx.get_plan(dt, H, W, M, nb)
+    if nbhd_path:
+        used = {"kernel": "nbhd_kernel", "half": [(0, 1), (1, 0)], "block": 512}
+    else:
+        ctx.set_plan(dt, M, nb, **plan)
+        used = ctx.get_plan(dt, H, W, M, nb)
+
+    def launch(buf):
+        if nbhd_path:
+            ctx.curve_nbhd_async(buf, M, half=[(0, 1), (1, 0)], out=out)
+        else:
+            ctx.curve_async(buf, M, nb, out=out)
     dev = torch.device("cuda", 0)
     src = (torch.from_numpy(img.view(np.int16)).to(dev).view(torch.uint16) if img.dtype == np.uint16
            else torch.from_numpy(img).to(dev))
@@ -106,15 +117,17 @@ def main():
     slots = np.zeros(MAXWG * SLOTS, np.uint64)
     waves = np.zeros(MAXWG * WAVES, np.uint64)
     for i in range(10):
-        ctx.curve_async(bufs[i % len(bufs)], M, nb, out=out)
+        launch(bufs[i % len(bufs)])
     torch.cuda.synchronize()
     rows = []
     for i in range(args.launches):
         assert lib.kohler_phase_clock_read(None, None, 1) == 0
-        ctx.curve_async(bufs[(10 + i) % len(bufs)], M, nb, out=out)
+        launch(bufs[(10 + i) % len(bufs)])
         torch.cuda.synchronize()
         assert lib.kohler_phase_clock_read(slots.ctypes.data, waves.ctypes.data, 0) == 0
-        rows.append(breakdown(slots, waves, used["grid"], used["block"] // 64))
+        # workgroups of the launch: those that stamped their entry
+        grid = used["grid"] if not nbhd_path else int(np.count_nonzero(slots.reshape(MAXWG, SLOTS)[:, 0]))
+        rows.append(breakdown(slots, waves, grid, used["block"] // 64))
         print(f"launch {i}: span {rows[-1]['span']:.2f} us", file=sys.stderr, flush=True)
     assert int(out["ints"][2]) == 0
     med = {k: float(np.median([r[k] for r in rows])) for k in rows[0]}
